@@ -1,0 +1,220 @@
+"""Throughput benchmark of 3D degridding on one MI355X.
+
+One step = one degrid of the paper-scale workload: 64 subgrids of
+512 x 512 x 4 complex64 (re, im ~ N(0,1)), separable Kaiser-Bessel G_uv
+(8 x 8, beta 18.72) and G_w (4 taps, beta 9.36) at oversampling 16, and
+floor(exp(U[ln 2^10, ln 2^18])) visibilities per subgrid, the first half of
+each subgrid's list on a folded line with constant step in [0.05, 0.5] cells
+and the rest uniform in the subgrid (seed 1). Inputs are resident in HBM
+before timing starts. Prints one JSON line.
+
+The roofline object prices the degrid kernel against HBM bandwidth with the
+algorithmic bytes of each visibility: its 8 x 8 x 4 complex64 neighbourhood
+(2048 B), the 8 x 8 float32 G_uv block (256 B), 4 float32 G_w taps (16 B),
+float64 (u, v, w) (24 B) and the complex64 output (8 B): 2352 B.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_VIS = {"c64": 2048 + 256 + 16 + 24 + 8, "cbf16": 1024 + 128 + 8 + 24 + 8, "cf16": 1024 + 128 + 8 + 24 + 8}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "degrid_fp32_paper_scale_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2102_12739_amd", "csrc", "degrid_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def upload_inputs(p, grid_dtype="c64", gcf_dtype="f32"):
+    import numpy as np
+    import torch
+    from paper_2102_12739_amd import workload as wl
+    dev = torch.device("cuda:0")
+    if grid_dtype == "c64":
+        sub = torch.from_numpy(p.subgrids).to(dev)
+    elif grid_dtype == "cbf16":
+        sub = torch.from_numpy(wl.complex_to_storage(p.subgrids, "cbf16").view(np.int16)).to(dev).view(torch.bfloat16)
+    else:
+        sub = torch.from_numpy(wl.complex_to_storage(p.subgrids, "cf16")).to(dev)
+    gdt = np.float32 if gcf_dtype == "f32" else np.float16
+    return (sub, torch.from_numpy(p.g_uv.astype(gdt)).to(dev), torch.from_numpy(p.g_w.astype(gdt)).to(dev),
+            torch.from_numpy(p.uvw).to(dev))
+
+
+def time_plan(plan, inputs, out, steps, warmup):
+    """Wall time per step (synchronised both sides) and kernel time per launch
+    (HIP events on the launch stream)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.execute(*inputs, out=out, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.execute(*inputs, out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, e0.elapsed_time(e1) / steps
+
+
+def copy_calibration(n_bytes=1 << 30):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters of a profiled run."""
+    import torch
+    a = torch.empty(n_bytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {n_bytes} bytes")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-variants", action="store_true", help="skip the bf16/fp16 storage runs")
+    ap.add_argument("--tune", action="store_true", help="let the plan time tile sizes first")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the degridding path shards by subgrid with no exchange; see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2102_12739_amd import workload as wl
+    from paper_2102_12739_amd.degrid import Plan
+
+    if args.copy_calibration:
+        copy_calibration()
+
+    t = time.perf_counter()
+    p = wl.paper_scale(seed=1)
+    log(f"workload {p.name}: S={p.n_subgrids} N={p.n_vis} generated in {time.perf_counter() - t:.1f}s")
+    inputs = upload_inputs(p)
+    out = torch.empty(p.n_vis, dtype=torch.complex64, device="cuda:0")
+    plan = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w)
+    tune_s = None
+    if args.tune:
+        t = time.perf_counter()
+        plan.tune(*inputs, out=out)
+        tune_s = time.perf_counter() - t
+    info = plan.info()
+    ms_step, ms_kernel = time_plan(plan, inputs, out, args.steps, args.warmup)
+    value = p.n_vis / (ms_step * 1e-3)
+    bytes_launch = BYTES_PER_VIS["c64"] * p.n_vis
+    achieved = bytes_launch / (ms_kernel * 1e-3) / 1e9
+    traffic = measured_traffic()
+    log(f"fp32: {ms_step:.4f} ms/step, kernel {ms_kernel:.4f} ms, {value:.4g} vis/s, "
+        f"{achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.2%} of HBM peak)")
+
+    result = {
+        "metric": "degridded visibilities/sec + HBM GB/s % peak (FP32 vs batched BF16) at rel-L2",
+        "value": value,
+        "unit": "visibilities/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": p.name, "subgrids": p.n_subgrids, "subgrid_shape": [p.n_v, p.n_u, p.n_w],
+                   "visibilities": p.n_vis, "os_uv": p.os_uv, "os_w": p.os_w, "grid_dtype": "c64",
+                   "gcf_dtype": "f32", "n_b": info["n_b"], "grid_blocks": info["grid_blocks"],
+                   "seed": 1},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "degrid_kernel<c64,f32>", "bytes_per_vis": BYTES_PER_VIS["c64"],
+                     "kernel_ms": ms_kernel},
+    }
+    if tune_s is not None:
+        result["config"]["tune_s"] = tune_s
+
+    # Low-precision storage of the same inputs (complex bf16 / fp16 subgrids,
+    # fp16 tables, fp32 accumulation).
+    variants = {}
+    if not args.no_variants:
+        for gdt in ("cbf16", "cf16"):
+            vin = upload_inputs(p, gdt, "f16")
+            vplan = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w, grid_dtype=gdt, gcf_dtype="f16")
+            vout = torch.empty_like(out)
+            vms, vkms = time_plan(vplan, vin, vout, args.steps, args.warmup)
+            variants[gdt] = {"value": p.n_vis / (vms * 1e-3), "ms_per_step": vms, "kernel_ms": vkms,
+                             "speedup_vs_fp32": ms_step / vms,
+                             "achieved_gbs": BYTES_PER_VIS[gdt] * p.n_vis / (vkms * 1e-3) / 1e9,
+                             "out": vout}
+            del vin
+            log(f"{gdt}: {vms:.4f} ms/step ({variants[gdt]['speedup_vs_fp32']:.2f}x fp32)")
+
+    if not args.no_cpu_baseline:
+        import oracle
+        a64 = p.subgrids.astype(np.complex128)
+        t = time.perf_counter()
+        ref, _ = oracle.degrid(a64, p.g_uv, p.g_w, p.uvw, p.offsets)
+        cpu_s = time.perf_counter() - t
+        got = out.cpu().numpy().astype(np.complex128)
+        rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        result["cpu_baseline"] = {"value": p.n_vis / cpu_s, "unit": "visibilities/s",
+                                  "cores": oracle.num_threads(), "kind": "oracle",
+                                  "sample": f"the whole workload ({p.n_vis} visibilities), FP64 C oracle, "
+                                            f"one run of {cpu_s:.2f} s"}
+        result["rel_l2"] = rel
+        for gdt, v in variants.items():
+            deq = wl.storage_to_complex128(wl.complex_to_storage(p.subgrids, gdt), gdt)
+            ref_q, _ = oracle.degrid(deq, p.g_uv.astype(np.float16), p.g_w.astype(np.float16), p.uvw, p.offsets)
+            gv = v["out"].cpu().numpy().astype(np.complex128)
+            v["rel_l2_vs_fp32_inputs"] = float(np.linalg.norm(gv - ref) / np.linalg.norm(ref))
+            v["rel_l2_vs_stored_inputs"] = float(np.linalg.norm(gv - ref_q) / np.linalg.norm(ref_q))
+    for v in variants.values():
+        v.pop("out", None)
+    if variants:
+        result["variants"] = variants
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

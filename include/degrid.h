@@ -1,0 +1,210 @@
+/*
+ * degrid.h -- C ABI of the MI355X (gfx950) 3D degridding library.
+ *
+ * The operation (Section 2 of the paper, "Implementation"): degridding forms
+ * each visibility as a weighted sum of regularly sampled values. The inputs
+ * are
+ *   - an oversampled gridding convolution function (GCF) for the uv plane,
+ *     G_uv, with support 8 x 8;
+ *   - an oversampled GCF for the w direction, G_w, with support 4;
+ *   - a stack of S subgrids of 512 x 512 x 4 complex values;
+ *   - for each subgrid, the list of its visibility coordinates [u, v, w].
+ * For every visibility the library computes the subgrid point g = [x, y, z]
+ * where the weighted sum starts and the positions of its weights inside the
+ * oversampled tables, then
+ *     V = sum_{tv<8} sum_{tu<8} sum_{tw<4}
+ *           G_w[o_w][tw] * G_uv[o_v][o_u][tv][tu] * A_s[y+tv][x+tu][z+tw].
+ * grid_adjoint applies the transpose of the same real linear map.
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - subgrid layout [S][n_v][n_u][n_w], w fastest, complex interleaved
+ *     (re, im);
+ *   - [u, v, w] are float64 in subgrid cells, origin at cell 0; per axis
+ *     k = floor(c * os) (exact in float64, os a power of two), cell
+ *     n = floor(k / os), oversample index o = k - n * os, first tap
+ *     n - (W/2 - 1);
+ *   - G_uv is indexed [o_v][o_u][t_v][t_u], G_w is indexed [o_w][t_w]; both
+ *     real;
+ *   - a visibility whose neighbourhood leaves the subgrid (or whose
+ *     coordinate is NaN or infinite) is out of range: its output is 0 and it
+ *     is counted (degrid_oob_count), it is not an error;
+ *   - the visibilities of subgrid s are rows vis_offsets[s] ..
+ *     vis_offsets[s+1]-1 of uvw and of the output (CSR offsets).
+ *
+ * Ownership: the caller owns every input and output buffer (device memory,
+ * e.g. from torch or hipMalloc). A plan owns its own device scratch (tile
+ * queue, queue cursors, out-of-range counter); only degrid_plan,
+ * degrid_batch_plan and degrid_tune allocate. degrid_execute, grid_adjoint
+ * and degrid_batch_execute allocate nothing and are asynchronous on the
+ * stream they are given. A plan or batch must be used by one stream at a
+ * time; calls that overlap on two streams race on the plan's scratch.
+ *
+ * Errors: every call returns a dg_status. Argument errors are detected on the
+ * host before any device work is queued. HIP errors map to DG_ERR_HIP;
+ * degrid_last_error() returns a thread-local detail string for the last
+ * failing call on the calling thread. No C++ exception crosses this ABI.
+ */
+#ifndef DEGRID_H
+#define DEGRID_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DG_OK = 0,
+    DG_ERR_INVALID_ARG = 1,   /* a pointer, size, offset list or descriptor field is invalid */
+    DG_ERR_UNSUPPORTED = 2,   /* valid but not implemented (e.g. support other than 8 / 4)   */
+    DG_ERR_NOMEM = 3,         /* device or host allocation failed                            */
+    DG_ERR_HIP = 4,           /* a HIP runtime call failed (no device, launch failure, ...)  */
+    DG_ERR_NOT_READY = 5      /* the object is not in a state that allows the call           */
+} dg_status;
+
+/* Storage type of subgrid values. Accumulation is always float32. */
+typedef enum {
+    DG_GRID_C64 = 0,   /* complex float32, 8 bytes per value            */
+    DG_GRID_CBF16 = 1, /* complex bfloat16 (re, im), 4 bytes per value  */
+    DG_GRID_CF16 = 2   /* complex float16 (re, im), 4 bytes per value   */
+} dg_grid_dtype;
+
+/* Storage type of the G_uv and G_w tables. */
+typedef enum {
+    DG_GCF_F32 = 0,
+    DG_GCF_F16 = 1
+} dg_gcf_dtype;
+
+/* Problem descriptor (Section 2: subgrid size, GCF supports and oversampling). */
+typedef struct {
+    int32_t n_v, n_u, n_w;          /* subgrid size; the paper's is 512, 512, 4                    */
+    int32_t support_uv, support_w;  /* GCF supports; must be 8 and 4 (else DG_ERR_UNSUPPORTED)     */
+    int32_t os_uv, os_w;            /* oversampling, powers of two in [1, 64]; tables are          */
+                                    /* G_uv[os_uv][os_uv][8][8] and G_w[os_w][4]                   */
+    int32_t grid_dtype;             /* dg_grid_dtype                                               */
+    int32_t gcf_dtype;              /* dg_gcf_dtype                                                */
+    int32_t n_b;                    /* visibilities per tile in [1, 64]; 0 = library choice        */
+    uint32_t flags;                 /* reserved, must be 0                                         */
+} dg_desc;
+
+typedef struct dg_plan_* dg_plan;    /* opaque, owned by the library */
+typedef struct dg_batch_* dg_batch;  /* opaque, owned by the library */
+
+/* Read-only facts about a plan (for logging and tests). */
+typedef struct {
+    int64_t n_subgrids;
+    int64_t n_vis;          /* vis_offsets[S]                                     */
+    int64_t n_tiles;        /* work items in the plan's queue                     */
+    int32_t n_b;            /* visibilities per tile actually used                */
+    int32_t kernel;         /* index of the gather kernel variant                 */
+    int32_t grid_blocks;    /* workgroups of the persistent launch                */
+    int32_t block_threads;  /* threads per workgroup                              */
+    int32_t n_queues;       /* per-XCD queues of the tile list                    */
+    int32_t device;         /* HIP device the plan's scratch lives on             */
+} dg_plan_info;
+
+/*
+ * Build a plan for S = n_subgrids subgrids.
+ *   d            descriptor (host); copied.
+ *   vis_offsets  host int64[S+1]; offsets[0] == 0, non-decreasing; copied.
+ *   stream       stream used for the plan's own uploads (may be NULL).
+ *   out          receives the plan; *out is set to NULL on failure.
+ * Allocates device scratch on the current HIP device. Synchronises 'stream'.
+ * Returns DG_ERR_INVALID_ARG for a bad descriptor or offsets,
+ * DG_ERR_UNSUPPORTED for supports other than 8 x 8 and 4, DG_ERR_NOMEM or
+ * DG_ERR_HIP when the device side cannot be set up.
+ */
+dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_offsets,
+                      hipStream_t stream, dg_plan* out);
+
+/*
+ * Degrid (Section 2; the launch geometry of Eq. (1) is replaced by a
+ * persistent, load-balanced tile queue).
+ *   subgrids  device [S][n_v][n_u][n_w] complex in the plan's grid dtype.
+ *   g_uv      device [os_uv][os_uv][8][8] in the plan's gcf dtype.
+ *   g_w       device [os_w][4] in the plan's gcf dtype.
+ *   uvw       device float64 [N][3], N = vis_offsets[S].
+ *   vis_out   device complex float32 [N]; every entry is written.
+ * Asynchronous on 'stream'; allocates nothing. The out-of-range count of this
+ * call replaces the plan's previous count.
+ */
+dg_status degrid_execute(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w,
+                         const double* uvw, void* vis_out, hipStream_t stream);
+
+/*
+ * Adjoint of degrid_execute (gridding): scatters G_w * G_uv * V_i onto the
+ * 8 x 8 x 4 neighbourhood of every in-range visibility.
+ *   vis          device complex float32 [N].
+ *   subgrids_out device complex float32 [S][n_v][n_u][n_w] (always float32,
+ *                whatever the plan's grid dtype).
+ *   accumulate   0: the output is overwritten (zeroed first, with a kernel);
+ *                1: contributions are added to its current contents.
+ * Float32 atomics make the summation order, and so the last bits, vary from
+ * run to run. Asynchronous on 'stream'; allocates nothing.
+ */
+dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void* g_w,
+                       const double* uvw, void* subgrids_out, int32_t accumulate,
+                       hipStream_t stream);
+
+/*
+ * Out-of-range visibilities seen by the last degrid_execute or grid_adjoint of
+ * this plan. Synchronises the stream of that call.
+ */
+dg_status degrid_oob_count(dg_plan p, int64_t* count);
+
+/* Plan facts; host only, does not touch the device. */
+dg_status degrid_plan_get_info(dg_plan p, dg_plan_info* info);
+
+/*
+ * Time the gather kernel variants and tile sizes on the given (real) inputs
+ * and keep the fastest in the plan (the tile list is rebuilt). Writes the
+ * choice to the on-disk cache named by DG_TUNE_CACHE when that is set.
+ * Synchronises 'stream'. vis_out is overwritten.
+ */
+dg_status degrid_tune(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w,
+                      const double* uvw, void* vis_out, hipStream_t stream);
+
+/* Release a plan and its device scratch (synchronises the device). NULL is a no-op. */
+dg_status degrid_destroy(dg_plan p);
+
+/*
+ * Batch several plans (independent problems with their own S, counts and
+ * oversampling, same grid and gcf dtypes) into one persistent launch. The
+ * plans must stay alive while the batch exists. Allocates the batch's tile
+ * list, queue and per-problem argument table.
+ */
+dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out);
+
+/*
+ * Degrid every problem of the batch in one launch.
+ *   args  host array of 5*n pointers: for problem i,
+ *         args[5i+0] subgrids, [5i+1] g_uv, [5i+2] g_w, [5i+3] uvw,
+ *         [5i+4] vis_out (all device pointers, as in degrid_execute).
+ * The persistent launch is captured into a HIP graph when the batch is
+ * planned and replayed on 'stream' by every call; a change of pointers
+ * re-uploads the per-problem argument table (a stream-ordered copy from the
+ * batch's pinned staging buffer) and keeps the graph.
+ */
+dg_status degrid_batch_execute(dg_batch b, const void* const* args, hipStream_t stream);
+
+/* Out-of-range count of the batch's last execute. Synchronises its stream. */
+dg_status degrid_batch_oob_count(dg_batch b, int64_t* count);
+
+/* Release a batch (not its plans). NULL is a no-op. */
+dg_status degrid_batch_destroy(dg_batch b);
+
+/* Static string naming a status code. */
+const char* degrid_status_str(dg_status s);
+
+/* Detail of the last failing call on this thread ("" if none). */
+const char* degrid_last_error(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t degrid_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEGRID_H */

@@ -1,0 +1,572 @@
+// Host runtime of the degridding library: the C ABI declared in degrid.h.
+//
+// Plans validate the problem descriptor and the CSR visibility offsets, cut
+// every subgrid's visibility list into tiles of n_b (Section 2: a block
+// processes N_b visibilities of one subgrid), split the tile list into one
+// contiguous queue per XCD balanced by visibility count, and own the device
+// scratch (tile list and control block). Execute calls only fill the launch
+// parameters and launch, so they allocate nothing.
+#include "degrid.h"
+#include "dg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+using namespace dg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dg_status fail(dg_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+dg_status hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? DG_ERR_NOMEM : DG_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool fault_injected(const char* what) {
+    const char* f = std::getenv("DG_FAULT_INJECT");
+    return f && std::strcmp(f, what) == 0;
+}
+
+int log2_exact(int32_t x) {
+    if (x < 1 || (x & (x - 1)) != 0) return -1;
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+uint32_t grid_elem_bytes(int32_t grid_dtype) { return grid_dtype == DG_GRID_C64 ? 8u : 4u; }
+uint32_t gcf_elem_bytes(int32_t gcf_dtype) { return gcf_dtype == DG_GCF_F32 ? 4u : 2u; }
+
+dg_status validate_desc(const dg_desc* d) {
+    if (!d) return fail(DG_ERR_INVALID_ARG, "descriptor is NULL");
+    if (d->flags != 0) return fail(DG_ERR_INVALID_ARG, "flags must be 0 (got %u)", d->flags);
+    if (d->support_uv != kSupportUV || d->support_w != kSupportW)
+        return fail(d->support_uv > 0 && d->support_w > 0 ? DG_ERR_UNSUPPORTED : DG_ERR_INVALID_ARG,
+                    "supports must be 8 (uv) and 4 (w), got %d and %d", d->support_uv, d->support_w);
+    if (d->n_v < kSupportUV || d->n_u < kSupportUV || d->n_w < kSupportW)
+        return fail(DG_ERR_INVALID_ARG, "subgrid %dx%dx%d is smaller than the support", d->n_v, d->n_u, d->n_w);
+    if (d->n_w != kSupportW)
+        return fail(DG_ERR_UNSUPPORTED, "n_w must equal the w support (4), got %d", d->n_w);
+    if (log2_exact(d->os_uv) < 0 || d->os_uv > 64 || log2_exact(d->os_w) < 0 || d->os_w > 64)
+        return fail(DG_ERR_INVALID_ARG, "oversampling must be a power of two in [1, 64], got %d and %d",
+                    d->os_uv, d->os_w);
+    if (d->grid_dtype < DG_GRID_C64 || d->grid_dtype > DG_GRID_CF16)
+        return fail(DG_ERR_INVALID_ARG, "unknown grid dtype %d", d->grid_dtype);
+    if (d->gcf_dtype < DG_GCF_F32 || d->gcf_dtype > DG_GCF_F16)
+        return fail(DG_ERR_INVALID_ARG, "unknown gcf dtype %d", d->gcf_dtype);
+    if (d->n_b < 0 || d->n_b > kMaxNb)
+        return fail(DG_ERR_INVALID_ARG, "n_b must be in [0, %d], got %d", kMaxNb, d->n_b);
+    const double cells = (double)d->n_v * d->n_u * d->n_w;
+    if (cells * 8.0 >= (double)kOutOfRange)
+        return fail(DG_ERR_UNSUPPORTED, "one subgrid must be smaller than %u bytes", kOutOfRange);
+    return DG_OK;
+}
+
+dg_status validate_offsets(int64_t n_sub, const int64_t* off) {
+    if (n_sub < 0) return fail(DG_ERR_INVALID_ARG, "n_subgrids is negative");
+    if (n_sub > 0x7FFFFFFF) return fail(DG_ERR_UNSUPPORTED, "too many subgrids");
+    if (!off) return fail(DG_ERR_INVALID_ARG, "vis_offsets is NULL");
+    if (off[0] != 0) return fail(DG_ERR_INVALID_ARG, "vis_offsets[0] must be 0");
+    for (int64_t s = 0; s < n_sub; ++s)
+        if (off[s + 1] < off[s])
+            return fail(DG_ERR_INVALID_ARG, "vis_offsets must be non-decreasing (at %lld)", (long long)s);
+    return DG_OK;
+}
+
+struct DeviceScratch {
+    Tile* tiles = nullptr;
+    Ctl* ctl = nullptr;
+    int64_t n_tiles = 0;
+};
+
+dg_status alloc_scratch(DeviceScratch& ds, const std::vector<Tile>& tiles, hipStream_t stream) {
+    if (fault_injected("alloc")) return fail(DG_ERR_NOMEM, "allocation failure injected (DG_FAULT_INJECT=alloc)");
+    hipError_t e;
+    if (!ds.ctl) {
+        e = hipMalloc(&ds.ctl, sizeof(Ctl));
+        if (e != hipSuccess) { ds.ctl = nullptr; return hip_fail(e, "hipMalloc(control block)"); }
+        e = hipMemsetAsync(ds.ctl, 0, sizeof(Ctl), stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(control block)");
+    }
+    if (ds.tiles) { (void)hipFree(ds.tiles); ds.tiles = nullptr; }
+    ds.n_tiles = (int64_t)tiles.size();
+    if (!tiles.empty()) {
+        e = hipMalloc(&ds.tiles, tiles.size() * sizeof(Tile));
+        if (e != hipSuccess) { ds.tiles = nullptr; return hip_fail(e, "hipMalloc(tile list)"); }
+        e = hipMemcpyAsync(ds.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tile list)");
+    }
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(plan upload)");
+    return DG_OK;
+}
+
+void free_scratch(DeviceScratch& ds) {
+    if (ds.tiles) (void)hipFree(ds.tiles);
+    if (ds.ctl) (void)hipFree(ds.ctl);
+    ds = DeviceScratch{};
+}
+
+}  // namespace
+
+struct dg_plan_ {
+    dg_desc desc{};
+    int64_t n_sub = 0;
+    std::vector<int64_t> offsets;
+    int32_t n_b = 0;
+    int32_t variant = 0;
+    int32_t blocks = 0;
+    int32_t blocks_cap = 0;    // resident workgroups of the whole device
+    int32_t device = 0;
+    QueueSpec q{};
+    DeviceScratch ds;
+    hipStream_t last_stream = nullptr;
+    bool launched = false;
+};
+
+struct dg_batch_ {
+    std::vector<dg_plan> plans;
+    int32_t grid_dtype = 0, gcf_dtype = 0;
+    int32_t device = 0;
+    int32_t blocks = 0;
+    QueueSpec q{};
+    DeviceScratch ds;
+    Problem* d_probs = nullptr;
+    Problem* h_probs = nullptr;     // pinned staging for argument uploads
+    hipEvent_t upload_done = nullptr;
+    bool uploaded = false;
+    std::vector<const void*> last_args;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool launched = false;
+};
+
+namespace {
+
+Problem problem_of(const dg_plan_* p, const void* subgrids, const void* g_uv, const void* g_w,
+                   const double* uvw, void* vis, void* grid_out) {
+    const dg_desc& d = p->desc;
+    Problem pr{};
+    pr.subgrids = subgrids;
+    pr.g_uv = g_uv;
+    pr.g_w = g_w;
+    pr.uvw = uvw;
+    pr.vis = vis;
+    pr.grid_out = grid_out;
+    pr.cells_per_sub = (int64_t)d.n_v * d.n_u * d.n_w;
+    pr.n_v = d.n_v;
+    pr.n_u = d.n_u;
+    pr.n_w = d.n_w;
+    pr.log2_os_uv = log2_exact(d.os_uv);
+    pr.log2_os_w = log2_exact(d.os_w);
+    pr.guv_bytes = (uint32_t)d.os_uv * d.os_uv * kSupportUV * kSupportUV * gcf_elem_bytes(d.gcf_dtype);
+    pr.sub_bytes = (uint32_t)(pr.cells_per_sub * grid_elem_bytes(d.grid_dtype));
+    // in range: first tap >= 0 and last tap < n along each axis
+    pr.hi_u = (double)(d.n_u - kSupportUV / 2);
+    pr.hi_v = (double)(d.n_v - kSupportUV / 2);
+    pr.hi_w = (double)(d.n_w - kSupportW / 2);
+    return pr;
+}
+
+// Workgroups for a persistent launch over n_tiles tiles: enough to fill the
+// device, never more than there are tiles for their wavefronts.
+int32_t blocks_for(int32_t cap, int64_t n_tiles) {
+    const int64_t useful = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap, useful));
+}
+
+dg_status device_capacity(int grid_kind, int gcf_kind, int variant, int32_t* device, int32_t* cap) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int n_cu = 0;
+    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(CU count)");
+    int fwd = 0, adj = 0;
+    e = degrid_kernel_occupancy(grid_kind, gcf_kind, variant, &fwd);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query (degrid)");
+    e = adjoint_kernel_occupancy(gcf_kind, 0, &adj);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query (adjoint)");
+    *device = dev;
+    *cap = (int32_t)std::max(1, n_cu * std::max(1, std::min(fwd, adj)));
+    return DG_OK;
+}
+
+std::string tune_key(const dg_plan_* p) {
+    std::ostringstream k;
+    int64_t n = p->offsets.back();
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= std::max<int64_t>(1, n)) ++lg;
+    k << "grid" << p->desc.grid_dtype << "_gcf" << p->desc.gcf_dtype << "_os" << p->desc.os_uv << "x"
+      << p->desc.os_w << "_S" << p->n_sub << "_log2N" << lg;
+    return k.str();
+}
+
+bool tune_cache_lookup(const std::string& key, int32_t* n_b, int32_t* variant) {
+    const char* path = std::getenv("DG_TUNE_CACHE");
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream ls(line);
+        std::string k;
+        int nb = 0, var = 0;
+        if (ls >> k >> nb >> var && k == key && nb >= 1 && nb <= kMaxNb && var >= 0 &&
+            var < degrid_variant_count()) {
+            *n_b = nb;
+            *variant = var;
+            found = true;   // the last entry for a key wins
+        }
+    }
+    return found;
+}
+
+void tune_cache_store(const std::string& key, int32_t n_b, int32_t variant) {
+    const char* path = std::getenv("DG_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << n_b << " " << variant << "\n";
+}
+
+// Default tile size when neither the caller nor the tuning cache fixes one.
+constexpr int32_t kDefaultNb = 64;
+
+dg_status rebuild_tiles(dg_plan_* p, int32_t n_b, hipStream_t stream) {
+    std::vector<Tile> tiles = build_tiles(p->n_sub, p->offsets.data(), n_b, 0);
+    dg_status s = alloc_scratch(p->ds, tiles, stream);
+    if (s != DG_OK) return s;
+    p->n_b = n_b;
+    p->q = split_queues(tiles);
+    p->blocks = blocks_for(p->blocks_cap, p->ds.n_tiles);
+    return DG_OK;
+}
+
+LaunchParams params_for(const dg_plan_* p, const Problem& pr) {
+    LaunchParams lp{};
+    lp.prob = pr;
+    lp.probs = nullptr;
+    lp.tiles = p->ds.tiles;
+    lp.ctl = p->ds.ctl;
+    lp.q = p->q;
+    return lp;
+}
+
+}  // namespace
+
+extern "C" {
+
+dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_offsets,
+                      hipStream_t stream, dg_plan* out) {
+    if (!out) return fail(DG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    dg_status s = validate_desc(d);
+    if (s != DG_OK) return s;
+    s = validate_offsets(n_subgrids, vis_offsets);
+    if (s != DG_OK) return s;
+    dg_plan_* p = new (std::nothrow) dg_plan_();
+    if (!p) return fail(DG_ERR_NOMEM, "host allocation of the plan failed");
+    p->desc = *d;
+    p->n_sub = n_subgrids;
+    p->offsets.assign(vis_offsets, vis_offsets + n_subgrids + 1);
+    int32_t n_b = d->n_b, variant = 0;
+    if (n_b == 0 && !tune_cache_lookup(tune_key(p), &n_b, &variant)) n_b = kDefaultNb;
+    p->variant = variant;
+    s = device_capacity(d->grid_dtype, d->gcf_dtype, variant, &p->device, &p->blocks_cap);
+    if (s == DG_OK) s = rebuild_tiles(p, n_b, stream);
+    if (s != DG_OK) {
+        free_scratch(p->ds);
+        delete p;
+        return s;
+    }
+    *out = p;
+    g_last_error.clear();
+    return DG_OK;
+}
+
+dg_status degrid_execute(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w,
+                         const double* uvw, void* vis_out, hipStream_t stream) {
+    if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");
+    if (p->ds.n_tiles == 0) return DG_OK;   // no visibilities: nothing to write
+    if (!subgrids || !g_uv || !g_w || !uvw || !vis_out)
+        return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+    const Problem pr = problem_of(p, subgrids, g_uv, g_w, uvw, vis_out, nullptr);
+    hipError_t e = launch_degrid(params_for(p, pr), p->desc.grid_dtype, p->desc.gcf_dtype, p->variant,
+                                 p->blocks, stream);
+    if (e != hipSuccess) return hip_fail(e, "degrid kernel launch");
+    p->last_stream = stream;
+    p->launched = true;
+    return DG_OK;
+}
+
+dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void* g_w,
+                       const double* uvw, void* subgrids_out, int32_t accumulate, hipStream_t stream) {
+    if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");
+    if (accumulate != 0 && accumulate != 1) return fail(DG_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+    if (!subgrids_out && p->n_sub > 0) return fail(DG_ERR_INVALID_ARG, "subgrids_out is NULL");
+    const int64_t out_bytes = p->n_sub * (int64_t)p->desc.n_v * p->desc.n_u * p->desc.n_w * 8;
+    if (!accumulate) {
+        hipError_t e = launch_zero(subgrids_out, out_bytes, stream);
+        if (e != hipSuccess) return hip_fail(e, "zero-fill kernel launch");
+    }
+    if (p->ds.n_tiles == 0) return DG_OK;
+    if (!vis || !g_uv || !g_w || !uvw) return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+    const Problem pr = problem_of(p, nullptr, g_uv, g_w, uvw, const_cast<void*>(vis), subgrids_out);
+    hipError_t e = launch_grid_adjoint(params_for(p, pr), p->desc.gcf_dtype, 0, p->blocks, stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+    p->last_stream = stream;
+    p->launched = true;
+    return DG_OK;
+}
+
+dg_status degrid_oob_count(dg_plan p, int64_t* count) {
+    if (!p || !count) return fail(DG_ERR_INVALID_ARG, "plan or count is NULL");
+    *count = 0;
+    if (!p->launched) return DG_OK;
+    hipError_t e = hipStreamSynchronize(p->last_stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    unsigned long long v = 0;
+    e = hipMemcpy(&v, &p->ds.ctl->oob.v[2], sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(out-of-range count)");
+    *count = (int64_t)v;
+    return DG_OK;
+}
+
+dg_status degrid_plan_get_info(dg_plan p, dg_plan_info* info) {
+    if (!p || !info) return fail(DG_ERR_INVALID_ARG, "plan or info is NULL");
+    info->n_subgrids = p->n_sub;
+    info->n_vis = p->offsets.back();
+    info->n_tiles = p->ds.n_tiles;
+    info->n_b = p->n_b;
+    info->kernel = p->variant;
+    info->grid_blocks = p->blocks;
+    info->block_threads = kBlockThreads;
+    info->n_queues = p->q.n_queues;
+    info->device = p->device;
+    return DG_OK;
+}
+
+dg_status degrid_tune(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w,
+                      const double* uvw, void* vis_out, hipStream_t stream) {
+    if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");
+    if (!subgrids || !g_uv || !g_w || !uvw || !vis_out)
+        return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+    if (p->offsets.back() == 0) return DG_OK;
+    static const int32_t kCandidates[] = {8, 16, 32, 64};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
+    float best_ms = 1e30f;
+    int32_t best_nb = p->n_b, best_var = p->variant;
+    dg_status st = DG_OK;
+    for (int var = 0; var < degrid_variant_count() && st == DG_OK; ++var) {
+        for (int32_t nb : kCandidates) {
+            p->variant = var;
+            st = rebuild_tiles(p, nb, stream);
+            if (st != DG_OK) break;
+            const int reps = 5;
+            for (int r = 0; r < 2 && st == DG_OK; ++r)
+                st = degrid_execute(p, subgrids, g_uv, g_w, uvw, vis_out, stream);
+            (void)hipEventRecord(e0, stream);
+            for (int r = 0; r < reps && st == DG_OK; ++r)
+                st = degrid_execute(p, subgrids, g_uv, g_w, uvw, vis_out, stream);
+            (void)hipEventRecord(e1, stream);
+            he = hipEventSynchronize(e1);
+            if (st != DG_OK) break;
+            if (he != hipSuccess) { st = hip_fail(he, "hipEventSynchronize"); break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best_nb = nb; best_var = var; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != DG_OK) return st;
+    p->variant = best_var;
+    st = rebuild_tiles(p, best_nb, stream);
+    if (st != DG_OK) return st;
+    tune_cache_store(tune_key(p), best_nb, best_var);
+    return DG_OK;
+}
+
+dg_status degrid_destroy(dg_plan p) {
+    if (!p) return DG_OK;
+    (void)hipDeviceSynchronize();
+    free_scratch(p->ds);
+    delete p;
+    return DG_OK;
+}
+
+dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
+    if (!out) return fail(DG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!plans || n <= 0) return fail(DG_ERR_INVALID_ARG, "need at least one plan");
+    if (n > 0xFFFF) return fail(DG_ERR_UNSUPPORTED, "at most 65535 problems per batch");
+    for (int32_t i = 0; i < n; ++i) {
+        if (!plans[i]) return fail(DG_ERR_INVALID_ARG, "plan %d is NULL", i);
+        if (plans[i]->desc.grid_dtype != plans[0]->desc.grid_dtype ||
+            plans[i]->desc.gcf_dtype != plans[0]->desc.gcf_dtype)
+            return fail(DG_ERR_INVALID_ARG, "plan %d has another grid or gcf dtype than plan 0", i);
+        if (plans[i]->device != plans[0]->device)
+            return fail(DG_ERR_INVALID_ARG, "plan %d lives on another device", i);
+    }
+    dg_batch_* b = new (std::nothrow) dg_batch_();
+    if (!b) return fail(DG_ERR_NOMEM, "host allocation of the batch failed");
+    b->plans.assign(plans, plans + n);
+    b->grid_dtype = plans[0]->desc.grid_dtype;
+    b->gcf_dtype = plans[0]->desc.gcf_dtype;
+    b->device = plans[0]->device;
+    std::vector<Tile> tiles;
+    for (int32_t i = 0; i < n; ++i) {
+        std::vector<Tile> t = build_tiles(plans[i]->n_sub, plans[i]->offsets.data(), plans[i]->n_b, (uint16_t)i);
+        tiles.insert(tiles.end(), t.begin(), t.end());
+    }
+    dg_status s = DG_OK;
+    hipError_t e;
+    auto bail = [&](dg_status st) {
+        degrid_batch_destroy(b);
+        return st;
+    };
+    s = alloc_scratch(b->ds, tiles, nullptr);
+    if (s != DG_OK) return bail(s);
+    b->q = split_queues(tiles);
+    b->blocks = blocks_for(plans[0]->blocks_cap, b->ds.n_tiles);
+    e = hipMalloc(&b->d_probs, sizeof(Problem) * n);
+    if (e != hipSuccess) { b->d_probs = nullptr; return bail(hip_fail(e, "hipMalloc(problem table)")); }
+    e = hipHostMalloc(&b->h_probs, sizeof(Problem) * n, hipHostMallocDefault);
+    if (e != hipSuccess) { b->h_probs = nullptr; return bail(hip_fail(e, "hipHostMalloc(problem table)")); }
+    e = hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming);
+    if (e != hipSuccess) { b->upload_done = nullptr; return bail(hip_fail(e, "hipEventCreate")); }
+    if (b->ds.n_tiles > 0) {
+        // One kernel node whose parameters point at the batch's own device
+        // table, queue and control block; arguments change through the table.
+        LaunchParams lp{};
+        lp.probs = b->d_probs;
+        lp.tiles = b->ds.tiles;
+        lp.ctl = b->ds.ctl;
+        lp.q = b->q;
+        e = hipGraphCreate(&b->graph, 0);
+        if (e != hipSuccess) { b->graph = nullptr; return bail(hip_fail(e, "hipGraphCreate")); }
+        hipStream_t cap = nullptr;
+        e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipStreamCreate"));
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = launch_degrid(lp, b->grid_dtype, b->gcf_dtype, plans[0]->variant, b->blocks, cap);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(cap, &g);
+            if (le != hipSuccess) e = le;
+            if (e == hipSuccess) {
+                (void)hipGraphDestroy(b->graph);
+                b->graph = g;
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+        }
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) return bail(hip_fail(e, "capturing the batch launch"));
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { b->exec = nullptr; return bail(hip_fail(e, "hipGraphInstantiate")); }
+    }
+    *out = b;
+    g_last_error.clear();
+    return DG_OK;
+}
+
+dg_status degrid_batch_execute(dg_batch b, const void* const* args, hipStream_t stream) {
+    if (!b || !args) return fail(DG_ERR_INVALID_ARG, "batch or args is NULL");
+    const size_t n = b->plans.size();
+    for (size_t i = 0; i < n; ++i) {
+        if (b->plans[i]->offsets.back() == 0) continue;
+        for (int k = 0; k < 5; ++k)
+            if (!args[5 * i + k]) return fail(DG_ERR_INVALID_ARG, "args[%zu] is NULL", 5 * i + k);
+    }
+    if (b->ds.n_tiles == 0) return DG_OK;
+    const bool same = b->uploaded && std::equal(b->last_args.begin(), b->last_args.end(), args);
+    hipError_t e;
+    if (!same) {
+        // the previous upload must have left the pinned staging buffer
+        e = hipEventSynchronize(b->upload_done);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(upload)");
+        for (size_t i = 0; i < n; ++i)
+            b->h_probs[i] = problem_of(b->plans[i], args[5 * i], args[5 * i + 1], args[5 * i + 2],
+                                       static_cast<const double*>(args[5 * i + 3]),
+                                       const_cast<void*>(args[5 * i + 4]), nullptr);
+        e = hipMemcpyAsync(b->d_probs, b->h_probs, sizeof(Problem) * n, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(problem table)");
+        e = hipEventRecord(b->upload_done, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord(upload)");
+        b->last_args.assign(args, args + 5 * n);
+        b->uploaded = true;
+    }
+    e = hipGraphLaunch(b->exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    b->last_stream = stream;
+    b->launched = true;
+    return DG_OK;
+}
+
+dg_status degrid_batch_oob_count(dg_batch b, int64_t* count) {
+    if (!b || !count) return fail(DG_ERR_INVALID_ARG, "batch or count is NULL");
+    *count = 0;
+    if (!b->launched) return DG_OK;
+    hipError_t e = hipStreamSynchronize(b->last_stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    unsigned long long v = 0;
+    e = hipMemcpy(&v, &b->ds.ctl->oob.v[2], sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(out-of-range count)");
+    *count = (int64_t)v;
+    return DG_OK;
+}
+
+dg_status degrid_batch_destroy(dg_batch b) {
+    if (!b) return DG_OK;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->upload_done) (void)hipEventDestroy(b->upload_done);
+    if (b->d_probs) (void)hipFree(b->d_probs);
+    if (b->h_probs) (void)hipHostFree(b->h_probs);
+    free_scratch(b->ds);
+    delete b;
+    return DG_OK;
+}
+
+const char* degrid_status_str(dg_status s) {
+    switch (s) {
+        case DG_OK: return "DG_OK";
+        case DG_ERR_INVALID_ARG: return "DG_ERR_INVALID_ARG";
+        case DG_ERR_UNSUPPORTED: return "DG_ERR_UNSUPPORTED";
+        case DG_ERR_NOMEM: return "DG_ERR_NOMEM";
+        case DG_ERR_HIP: return "DG_ERR_HIP";
+        case DG_ERR_NOT_READY: return "DG_ERR_NOT_READY";
+    }
+    return "DG_ERR_UNKNOWN";
+}
+
+const char* degrid_last_error(void) { return g_last_error.c_str(); }
+
+int32_t degrid_version(void) { return 100; }
+
+}  // extern "C"

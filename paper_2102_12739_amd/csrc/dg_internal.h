@@ -1,0 +1,74 @@
+// Internal types shared by the host runtime and the gfx950 kernels. The tile
+// list and queue split they consume are described in plan_logic.h.
+#pragma once
+
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+#include "plan_logic.h"
+
+namespace dg {
+
+constexpr int kSupportUV = 8;   // G_uv support per axis (Section 2)
+constexpr int kSupportW = 4;    // G_w support (Section 2)
+constexpr int kWave = 64;       // CDNA wavefront
+constexpr int kBlockThreads = 256;
+constexpr int kWavesPerBlock = kBlockThreads / kWave;
+
+// Invalid-offset sentinel for hardware bounds-checked (buffer) loads: any
+// offset at or above a resource's size returns zero. Subgrids and tables are
+// limited to less than this many bytes.
+constexpr uint32_t kOutOfRange = 0x40000000u;
+
+// Everything a kernel needs to know about one problem.
+struct Problem {
+    const void* subgrids;   // [S][n_v][n_u][n_w] in the grid dtype
+    const void* g_uv;       // [os_uv][os_uv][8][8] in the gcf dtype
+    const void* g_w;        // [os_w][4] in the gcf dtype
+    const double* uvw;      // [N][3]
+    void* vis;              // complex float32 [N]: degrid output / adjoint input
+    void* grid_out;         // complex float32 [S][n_v][n_u][n_w]: adjoint output
+    int64_t cells_per_sub;  // n_v * n_u * n_w
+    int32_t n_v, n_u, n_w;
+    int32_t log2_os_uv, log2_os_w;
+    uint32_t guv_bytes;     // size of G_uv in bytes
+    uint32_t sub_bytes;     // size of one subgrid in bytes (grid dtype)
+    int32_t pad_;
+    double hi_u, hi_v, hi_w;  // exclusive upper bounds of in-range coordinates
+};
+
+// Device control block of a plan or batch: queue cursors (one 128-byte line
+// each, so atomics from different XCDs do not share a line), the count of
+// finished workgroups, and the out-of-range counters. The last workgroup of
+// every launch resets the cursors and the counters, so a launch needs no
+// separate reset and can be replayed from a graph.
+struct alignas(128) CtlLine { uint32_t v[32]; };
+struct Ctl {
+    CtlLine cursor[kMaxQueues];
+    CtlLine done;
+    CtlLine oob;   // v[0..1]: running count (u64), v[2..3]: count of the last launch
+};
+
+struct LaunchParams {
+    Problem prob;               // used when probs == nullptr
+    const Problem* probs;       // per-problem table of a batch
+    const Tile* tiles;
+    Ctl* ctl;
+    QueueSpec q;
+};
+
+enum GridKind : int32_t { kGridC64 = 0, kGridCBF16 = 1, kGridCF16 = 2 };
+enum GcfKind : int32_t { kGcfF32 = 0, kGcfF16 = 1 };
+
+// Kernel launchers (defined in degrid_kernels.hip).
+hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int variant,
+                         int blocks, hipStream_t stream);
+hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant, int blocks,
+                               hipStream_t stream);
+hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t stream);
+hipError_t degrid_kernel_occupancy(int grid_kind, int gcf_kind, int variant, int* blocks_per_cu);
+hipError_t adjoint_kernel_occupancy(int gcf_kind, int variant, int* blocks_per_cu);
+int degrid_variant_count();
+int adjoint_variant_count();
+
+}  // namespace dg

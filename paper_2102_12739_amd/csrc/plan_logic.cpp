@@ -1,0 +1,50 @@
+#include "plan_logic.h"
+
+#include <algorithm>
+
+namespace dg {
+
+std::vector<Tile> build_tiles(int64_t n_sub, const int64_t* off, int nb, uint16_t problem) {
+    std::vector<Tile> tiles;
+    int64_t n = 0;
+    for (int64_t s = 0; s < n_sub; ++s) n += (off[s + 1] - off[s] + nb - 1) / nb;
+    tiles.reserve((size_t)n);
+    for (int64_t s = 0; s < n_sub; ++s)
+        for (int64_t b = off[s]; b < off[s + 1]; b += nb) {
+            Tile t;
+            t.begin = b;
+            t.sub = (int32_t)s;
+            t.count = (uint16_t)std::min<int64_t>(nb, off[s + 1] - b);
+            t.problem = problem;
+            tiles.push_back(t);
+        }
+    return tiles;
+}
+
+QueueSpec split_queues(const std::vector<Tile>& tiles) {
+    QueueSpec q{};
+    const int64_t n_tiles = (int64_t)tiles.size();
+    const int nq = (int)std::min<int64_t>(kMaxQueues, std::max<int64_t>(1, n_tiles));
+    q.n_queues = nq;
+    int64_t total = 0;
+    for (const Tile& t : tiles) total += t.count;
+    int64_t acc = 0;
+    int cur = 0;
+    q.begin[0] = 0;
+    for (int64_t i = 0; i < n_tiles && cur < nq - 1; ++i) {
+        acc += tiles[(size_t)i].count;
+        // close queue 'cur' once it holds its share of the visibilities
+        if (acc * nq >= total * (int64_t)(cur + 1)) {
+            q.end[cur] = (int32_t)(i + 1);
+            ++cur;
+            q.begin[cur] = (int32_t)(i + 1);
+        }
+    }
+    for (int c = cur; c < nq; ++c) {
+        if (c > cur) q.begin[c] = (int32_t)n_tiles;
+        q.end[c] = (int32_t)n_tiles;
+    }
+    return q;
+}
+
+}  // namespace dg

@@ -1,0 +1,44 @@
+// Host-side work decomposition (plain C++, no HIP): the tile list and its
+// split into per-XCD queues. Kept free of HIP so that it can be built and
+// tested on a machine without a GPU.
+//
+// Section 2 of the paper gives each thread block N_b visibilities of one
+// subgrid and launches max_S(N_vis,S / N_b) x S blocks (Eq. (1)); with uneven
+// counts most of those blocks find no work. Here the same N_b-visibility
+// tiles form one list that a persistent launch drains.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+namespace dg {
+
+constexpr int kMaxQueues = 8;   // one tile queue per XCD of an MI355X
+constexpr int kMaxNb = 64;      // a tile fits one wavefront's coordinate stage
+
+// One work item: up to n_b consecutive visibilities of one subgrid.
+struct Tile {
+    int64_t begin;     // first visibility (row of uvw and of the output)
+    int32_t sub;       // subgrid index inside its problem
+    uint16_t count;    // visibilities in the tile, 1..kMaxNb
+    uint16_t problem;  // problem index inside a batch (0 for a single plan)
+};
+static_assert(sizeof(Tile) == 16, "Tile must stay 16 bytes");
+
+struct QueueSpec {
+    int32_t n_queues;
+    int32_t begin[kMaxQueues];  // first tile of queue q
+    int32_t end[kMaxQueues];    // one past the last tile of queue q
+};
+
+// Cut the visibilities of each of n_sub subgrids (CSR offsets off[0..n_sub])
+// into tiles of at most nb consecutive visibilities, in subgrid order.
+std::vector<Tile> build_tiles(int64_t n_sub, const int64_t* off, int nb, uint16_t problem);
+
+// Split a tile list into up to kMaxQueues contiguous queues holding about
+// equal numbers of visibilities (empty queues only when there are fewer
+// tiles than queues).
+QueueSpec split_queues(const std::vector<Tile>& tiles);
+
+}  // namespace dg

@@ -1,0 +1,190 @@
+"""C-ABI checks that need no GPU: exported symbols, struct layout, argument
+validation, status strings, and the host-side tile decomposition."""
+
+import ctypes
+import json
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "degrid.h")
+CSRC = os.path.join(ROOT, "paper_2102_12739_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def dg():
+    from paper_2102_12739_amd import degrid
+    if not os.path.exists(degrid.library_path()):
+        from paper_2102_12739_amd import build
+        build.build()
+    degrid.lib()
+    return degrid
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([A-Za-z_]\w*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n.startswith(("degrid_", "grid_"))))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("degrid_plan", "degrid_execute", "grid_adjoint", "degrid_oob_count", "degrid_destroy",
+                 "degrid_batch_plan", "degrid_batch_execute", "degrid_status_str", "degrid_last_error"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(dg):
+    lib = ctypes.CDLL(dg.library_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layout_matches_ctypes(tmp_path):
+    exe = tmp_path / "abi_layout"
+    subprocess.run(["gcc", "-std=c99", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                    "-I", "/opt/rocm/include", os.path.join(ROOT, "tests", "cpp", "abi_layout.c"),
+                    "-o", str(exe)], check=True)
+    got = json.loads(subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout)
+    from paper_2102_12739_amd.degrid import DgDesc, DgPlanInfo
+    assert got["dg_desc"] == [ctypes.sizeof(DgDesc), DgDesc.os_uv.offset, DgDesc.grid_dtype.offset,
+                              DgDesc.n_b.offset, DgDesc.flags.offset, DgDesc.support_w.offset]
+    assert got["dg_plan_info"] == [ctypes.sizeof(DgPlanInfo), DgPlanInfo.n_tiles.offset, DgPlanInfo.n_b.offset,
+                                   DgPlanInfo.n_queues.offset, DgPlanInfo.device.offset]
+
+
+def test_status_strings_and_version(dg):
+    L = dg.lib()
+    for code, name in dg._STATUS.items():
+        assert L.degrid_status_str(code).decode() == name
+    assert L.degrid_version() >= 100
+
+
+def _plan_raw(dg, desc, offsets, n_sub=None):
+    off = np.asarray(offsets, dtype=np.int64)
+    h = ctypes.c_void_p()
+    st = dg.lib().degrid_plan(ctypes.byref(desc) if desc is not None else None,
+                              len(off) - 1 if n_sub is None else n_sub,
+                              off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), None, ctypes.byref(h))
+    return st, h
+
+
+def _desc(dg, **kw):
+    base = dict(n_v=512, n_u=512, n_w=4, support_uv=8, support_w=4, os_uv=16, os_w=16,
+                grid_dtype=0, gcf_dtype=0, n_b=32, flags=0)
+    base.update(kw)
+    return dg.DgDesc(**base)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(os_uv=12), 1), (dict(os_w=0), 1), (dict(os_uv=128), 1), (dict(flags=1), 1),
+    (dict(n_b=65), 1), (dict(n_b=-1), 1), (dict(grid_dtype=3), 1), (dict(gcf_dtype=2), 1),
+    (dict(n_v=7), 1), (dict(support_uv=6), 2), (dict(support_w=6), 2), (dict(n_w=8), 2),
+    (dict(support_uv=0), 1), (dict(n_v=8192, n_u=8192), 2),
+])
+def test_invalid_descriptors_are_rejected_before_device_work(dg, kw, status):
+    st, h = _plan_raw(dg, _desc(dg, **kw), [0, 10])
+    assert st == status
+    assert h.value is None
+    assert dg.lib().degrid_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("offsets,n_sub", [([1, 10], None), ([0, 10, 5], None), ([0, 3], -1)])
+def test_invalid_offsets_are_rejected(dg, offsets, n_sub):
+    st, h = _plan_raw(dg, _desc(dg), offsets, n_sub)
+    assert st == 1 and h.value is None
+
+
+def test_null_arguments(dg):
+    L = dg.lib()
+    st, _ = _plan_raw(dg, None, [0, 1])
+    assert st == 1
+    assert L.degrid_execute(None, 1, 1, 1, 1, 1, None) == 1
+    assert L.grid_adjoint(None, 1, 1, 1, 1, 1, 0, None) == 1
+    assert L.degrid_oob_count(None, None) == 1
+    assert L.degrid_plan_get_info(None, None) == 1
+    assert L.degrid_destroy(None) == 0
+    assert L.degrid_batch_destroy(None) == 0
+    assert L.degrid_batch_plan(None, 0, None) == 1
+
+
+def test_plan_without_device_reports_hip_error(dg):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, h = _plan_raw(dg, _desc(dg), [0, 100])
+    assert st == 4 and h.value is None
+    assert "hip" in dg.lib().degrid_last_error().decode().lower()
+
+
+def test_python_plan_raises_degrid_error(dg):
+    with pytest.raises(dg.DegridError) as e:
+        dg.Plan([0, 10], os_uv=12)
+    assert e.value.status == 1
+
+
+# ---------------------------------------------------------------------------
+# Host work decomposition (plain C++, built with g++)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def plan_logic(tmp_path_factory):
+    exe = tmp_path_factory.mktemp("pl") / "plan_logic_check"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-I", CSRC,
+                    "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    os.path.join(ROOT, "tests", "cpp", "plan_logic_check.cpp"),
+                    os.path.join(CSRC, "plan_logic.cpp"), "-o", str(exe)], check=True)
+
+    def run(nb, counts):
+        r = subprocess.run([str(exe), str(nb), *map(str, counts)], capture_output=True, text=True, check=True)
+        return json.loads(r.stdout)
+    return run
+
+
+@pytest.mark.parametrize("nb,counts", [
+    (32, [1024, 1024]), (64, [0, 1, 63, 64, 65, 0, 129]), (1, [5, 0, 3]), (7, [100]),
+    (32, []), (16, [0, 0, 0]), (64, list(np.random.default_rng(0).integers(0, 5000, 64))),
+])
+def test_tiles_cover_each_subgrid_exactly_once(plan_logic, nb, counts):
+    out = plan_logic(nb, counts)
+    tiles = out["tiles"]
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    covered = np.zeros(int(off[-1]), dtype=np.int64)
+    for begin, sub, count, problem in tiles:
+        assert problem == 3
+        assert 1 <= count <= nb
+        assert off[sub] <= begin and begin + count <= off[sub + 1]
+        covered[begin:begin + count] += 1
+    assert np.all(covered == 1)
+    # tiles are in subgrid order and only the last tile of a subgrid is short
+    for (b0, s0, c0, _), (b1, s1, c1, _) in zip(tiles, tiles[1:]):
+        assert (s1, b1) > (s0, b0)
+        if s1 == s0:
+            assert c0 == nb
+
+
+@pytest.mark.parametrize("nb,counts", [
+    (32, list(np.random.default_rng(1).integers(2 ** 10, 2 ** 18, 64))), (64, [10]), (8, [3, 3, 3]),
+    (32, [0] * 5 + [100000] + [0] * 5), (16, list(np.random.default_rng(2).integers(0, 300, 40))),
+])
+def test_queues_partition_the_tile_list_and_balance_visibilities(plan_logic, nb, counts):
+    out = plan_logic(nb, counts)
+    n_tiles = len(out["tiles"])
+    nq, begin, end = out["n_queues"], out["begin"], out["end"]
+    assert 1 <= nq <= 8
+    assert nq == min(8, max(1, n_tiles))
+    assert begin[0] == 0 and end[-1] == n_tiles
+    for q in range(nq):
+        assert begin[q] <= end[q]
+        if q:
+            assert begin[q] == end[q - 1]
+    vis = np.array([t[2] for t in out["tiles"]])
+    if n_tiles >= 8 * 4:
+        per_q = [vis[begin[q]:end[q]].sum() for q in range(nq)]
+        share = vis.sum() / nq
+        assert max(per_q) <= share + nb and min(per_q) >= share - nb

@@ -1,0 +1,196 @@
+"""GPU parity of degridding: the HIP path through the C ABI against the FP64
+oracle on the same seeded inputs (Section 2 defines the operation)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2102_12739_amd import workload as wl
+from tests.gpu_common import REL_L2_FP32, announce, device, plan_for, rel_l2, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(p, **plan_kw):
+    t = upload(p)
+    plan = plan_for(p, **plan_kw)
+    vis = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"])
+    torch.cuda.synchronize()
+    return plan, vis.cpu().numpy()
+
+
+def test_plain_line_two_subgrids_matches_oracle():
+    p = wl.plain_line(seed=0)
+    announce(f"plain line S=2 N={p.n_vis}")
+    plan, got = _run(p)
+    ref, oob = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert rel_l2(got, ref) <= REL_L2_FP32
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
+    assert plan.oob_count() == oob == 0
+
+
+def test_paper_scale_full_size_matches_oracle():
+    """64 subgrids of 512x512x4, 2^10..2^18 visibilities each (about 3.2 M), the
+    launch configuration the benchmark times; every output is checked."""
+    p = wl.paper_scale(seed=1)
+    announce(f"paper scale S=64 N={p.n_vis}")
+    plan, got = _run(p)
+    ref, oob = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert rel_l2(got, ref) <= REL_L2_FP32
+    per = np.abs(got - ref) / (np.abs(ref) + 1e-3 * np.sqrt(np.mean(np.abs(ref) ** 2)))
+    assert np.max(per) <= 1e-3
+    assert plan.oob_count() == oob == 0
+    info = plan.info()
+    assert info["n_vis"] == p.n_vis and info["n_queues"] == 8
+
+
+@pytest.mark.parametrize("n_b", [1, 7, 8, 33, 64])
+def test_ragged_tiles_and_tile_sizes(n_b):
+    counts = [0, 1, 63, 64, 65, 1000, 7]
+    p = wl.make_problem("ragged", counts, seed=11, kind="mixed", n_v=40, n_u=72)
+    announce(f"ragged n_b={n_b}")
+    plan, got = _run(p, n_b=n_b)
+    assert plan.info()["n_b"] == n_b
+    ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert rel_l2(got, ref) <= REL_L2_FP32
+    # the tile size changes the work split only, never a visibility's sum
+    _, got64 = _run(p, n_b=64)
+    assert np.array_equal(got, got64)
+
+
+@pytest.mark.parametrize("os_uv,os_w", [(1, 1), (2, 8), (8, 2), (32, 32), (64, 4)])
+def test_oversampling_factors(os_uv, os_w):
+    p = wl.make_problem("os", [300, 211], seed=12, kind="uniform", n_v=24, n_u=40,
+                        os_uv=os_uv, os_w=os_w)
+    announce(f"oversampling {os_uv}/{os_w}")
+    plan, got = _run(p)
+    ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert rel_l2(got, ref) <= REL_L2_FP32
+
+
+def test_random_nonseparable_tables_and_nonsquare_subgrids():
+    rng = np.random.default_rng(13)
+    p = wl.make_problem("rand-tables", [500, 500, 500], seed=13, kind="uniform", n_v=20, n_u=56,
+                        os_uv=8, os_w=4)
+    p.g_uv = wl.random_gcf_uv(rng, 8)
+    p.g_w = wl.random_gcf_w(rng, 4)
+    announce("random tables")
+    _, got = _run(p)
+    ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert rel_l2(got, ref) <= REL_L2_FP32
+
+
+def test_delta_subgrid_picks_the_oracle_tap_at_oversample_boundaries():
+    """Coordinates at j/os and one float64 ulp below: the GPU's float64 index
+    conversion must choose the same cell and table entry as the oracle."""
+    rng = np.random.default_rng(14)
+    os_uv = os_w = 16
+    n_v, n_u, n_w = 32, 32, 4
+    g_uv = wl.random_gcf_uv(rng, os_uv)
+    g_w = wl.random_gcf_w(rng, os_w)
+    n = 256
+    ju = rng.integers(3 * os_uv + 1, 28 * os_uv, n)
+    jv = rng.integers(3 * os_uv + 1, 28 * os_uv, n)
+    jw = rng.integers(os_w + 1, 2 * os_w, n)
+    on = np.stack([ju / os_uv, jv / os_uv, jw / os_w], 1)
+    uvw = np.concatenate([on, np.nextafter(on, -np.inf)])
+    sub = np.zeros((1, n_v, n_u, n_w), np.complex64)
+    sub[0, 10:22, 10:22, :] = rng.standard_normal((12, 12, 4)).astype(np.float32)
+    p = wl.Problem("boundaries", n_v, n_u, n_w, os_uv, os_w, np.array([0, 2 * n]), uvw, g_uv, g_w, sub)
+    announce("oversample boundaries")
+    _, got = _run(p)
+    ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    scale = np.abs(ref) + 1e-6
+    assert np.max(np.abs(got - ref) / scale) <= 1e-4
+
+
+def test_out_of_range_visibilities_are_zero_and_counted():
+    n_v = n_u = 512
+    good = [3.0, np.nextafter(508.0, 0.0), 255.5]
+    bad = [np.nextafter(3.0, 0.0), 508.0, -1.0, 1e300, np.nan, np.inf, -np.inf]
+    rows, valid = [], []
+    for u in good + bad:
+        rows.append((u, 100.25, 1.5)); valid.append(u in good)
+        rows.append((100.25, u, 1.5)); valid.append(u in good)
+    for w in [1.0, np.nextafter(2.0, 0.0), np.nextafter(1.0, 0.0), 2.0, np.nan]:
+        rows.append((100.25, 100.25, w)); valid.append(w in (1.0, np.nextafter(2.0, 0.0)))
+    uvw = np.array(rows)
+    sub = np.ones((1, n_v, n_u, 4), np.complex64)
+    p = wl.Problem("oob", n_v, n_u, 4, 16, 16, np.array([0, len(rows)]), uvw, wl.gcf_uv(16), wl.gcf_w(16), sub)
+    announce("out of range")
+    plan, got = _run(p)
+    ref, oob = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    valid = np.array(valid)
+    assert plan.oob_count() == oob == int(np.sum(~valid))
+    assert np.all(got[~valid] == 0)
+    assert rel_l2(got, ref) <= REL_L2_FP32
+
+
+def test_empty_problem_and_empty_subgrids():
+    p = wl.make_problem("empty", [0, 0, 0], seed=15, kind="uniform", n_v=16, n_u=16)
+    announce("empty")
+    plan, got = _run(p)
+    assert got.shape == (0,) and plan.info()["n_tiles"] == 0 and plan.oob_count() == 0
+
+
+def test_single_visibility_and_last_subgrid_only():
+    p = wl.make_problem("single", [0, 0, 1], seed=16, kind="uniform", n_v=16, n_u=16)
+    _, got = _run(p)
+    ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert rel_l2(got, ref) <= REL_L2_FP32
+
+
+def test_repeated_launches_reset_the_queue_and_counts():
+    p = wl.make_problem("repeat", [2000, 1500, 3], seed=17, kind="mixed", n_v=64, n_u=64)
+    p.uvw[5] = (np.nan, 10.0, 1.5)
+    t = upload(p)
+    plan = plan_for(p)
+    ref, oob = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    first = None
+    for _ in range(5):
+        out = torch.full((p.n_vis,), float("nan"), dtype=torch.complex64, device=device())
+        plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"], out=out)
+        got = out.cpu().numpy()
+        assert rel_l2(got, ref) <= REL_L2_FP32
+        assert plan.oob_count() == oob == 1
+        if first is None:
+            first = got
+        assert np.array_equal(got, first)
+
+
+def test_non_default_stream():
+    p = wl.make_problem("stream", [777, 1234], seed=18, kind="mixed", n_v=48, n_u=48)
+    t = upload(p)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        plan = plan_for(p)
+        vis = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"])
+    s.synchronize()
+    ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert rel_l2(vis.cpu().numpy(), ref) <= REL_L2_FP32
+
+
+def test_argument_checks_raise():
+    from paper_2102_12739_amd.degrid import DegridError
+    p = wl.make_problem("args", [10], seed=19, kind="uniform", n_v=16, n_u=16)
+    t = upload(p)
+    plan = plan_for(p)
+    with pytest.raises(ValueError):
+        plan.execute(t["sub"][:, :8], t["g_uv"], t["g_w"], t["uvw"])
+    with pytest.raises(TypeError):
+        plan.execute(t["sub"], t["g_uv"].double(), t["g_w"], t["uvw"])
+    import ctypes
+    from paper_2102_12739_amd.degrid import lib
+    assert lib().degrid_execute(plan.handle, 0, 1, 1, 1, 1, None) == 1
+    del DegridError
+
+
+def test_injected_allocation_failure(monkeypatch):
+    from paper_2102_12739_amd.degrid import DegridError
+    monkeypatch.setenv("DG_FAULT_INJECT", "alloc")
+    p = wl.make_problem("nomem", [10], seed=20, kind="uniform", n_v=16, n_u=16)
+    with pytest.raises(DegridError) as e:
+        plan_for(p)
+    assert e.value.status == 3
