@@ -38,6 +38,7 @@
  * and degrid_batch_execute allocate nothing and are asynchronous on the
  * stream they are given. A plan or batch must be used by one stream at a
  * time; calls that overlap on two streams race on the plan's scratch.
+ * degrid_plan_sort also allocates (the plan's work-order permutation).
  *
  * Errors: every call returns a dg_status. Argument errors are detected on the
  * host before any device work is queued. HIP errors map to DG_ERR_HIP;
@@ -102,6 +103,8 @@ typedef struct {
     int32_t block_threads;  /* threads per workgroup                              */
     int32_t n_queues;       /* per-XCD queues of the tile list                    */
     int32_t device;         /* HIP device the plan's scratch lives on             */
+    int32_t sorted;         /* 1 if degrid_plan_sort set a work order             */
+    int32_t n_kernels;      /* number of gather kernel variants                   */
 } dg_plan_info;
 
 /*
@@ -153,6 +156,23 @@ dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void*
  */
 dg_status degrid_oob_count(dg_plan p, int64_t* count);
 
+/*
+ * Reorder the plan's work for locality: within each subgrid, visibilities are
+ * processed in the Z-order (Morton order) of the cell that holds (u, v), so a
+ * tile holds visibilities that are close in the subgrid and consecutive tiles
+ * cover neighbouring regions (Section 2 notes that one grid point may serve
+ * several visibilities; this makes that reuse happen in cache).
+ *   uvw  device float64 [N][3], the coordinates later calls will use; NULL
+ *        drops the work order (back to input order).
+ * Every output stays in input order and every result is unchanged (each
+ * visibility's sum does not depend on the order); only speed depends on uvw
+ * matching the coordinates passed to later calls. Allocates the plan's
+ * permutation (4 bytes per visibility) and temporary sort buffers;
+ * synchronises 'stream'. DG_ERR_UNSUPPORTED if N >= 2^32.
+ * Batches built from this plan before the call must be rebuilt.
+ */
+dg_status degrid_plan_sort(dg_plan p, const double* uvw, hipStream_t stream);
+
 /* Plan facts; host only, does not touch the device. */
 dg_status degrid_plan_get_info(dg_plan p, dg_plan_info* info);
 
@@ -164,6 +184,17 @@ dg_status degrid_plan_get_info(dg_plan p, dg_plan_info* info);
  */
 dg_status degrid_tune(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w,
                       const double* uvw, void* vis_out, hipStream_t stream);
+
+/*
+ * Choose the gather kernel variant and the tile size by hand (what
+ * degrid_tune chooses by timing). kernel: index in [0, number of variants),
+ * or -1 to keep the current one; n_b: visibilities per tile in [1, 64], or 0
+ * to keep the current one. Variants differ in how much LDS each wavefront
+ * uses to stage a tile's cells (variant 0 stages nothing); results are the
+ * same for every variant. Rebuilds the tile list (allocates); synchronises
+ * 'stream'. Batches built from this plan before the call must be rebuilt.
+ */
+dg_status degrid_plan_set_kernel(dg_plan p, int32_t kernel, int32_t n_b, hipStream_t stream);
 
 /* Release a plan and its device scratch (synchronises the device). NULL is a no-op. */
 dg_status degrid_destroy(dg_plan p);
@@ -187,6 +218,8 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out);
  * batch's pinned staging buffer) and keeps the graph.
  */
 dg_status degrid_batch_execute(dg_batch b, const void* const* args, hipStream_t stream);
+/* (DG_ERR_NOT_READY if one of the plans was re-sorted or re-tuned after the
+ * batch was planned.) */
 
 /* Out-of-range count of the batch's last execute. Synchronises its stream. */
 dg_status degrid_batch_oob_count(dg_batch b, int64_t* count);

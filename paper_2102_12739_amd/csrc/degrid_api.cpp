@@ -134,17 +134,23 @@ struct dg_plan_ {
     std::vector<int64_t> offsets;
     int32_t n_b = 0;
     int32_t variant = 0;
-    int32_t blocks = 0;
-    int32_t blocks_cap = 0;    // resident workgroups of the whole device
+    int32_t blocks = 0;                    // persistent grid of the degrid kernel
+    int32_t blocks_adj = 0;                // persistent grid of the adjoint kernel
+    int32_t cap[kMaxVariants] = {};        // resident workgroups per degrid variant
+    int32_t cap_adj = 0;
     int32_t device = 0;
     QueueSpec q{};
     DeviceScratch ds;
     hipStream_t last_stream = nullptr;
     bool launched = false;
+    uint32_t* d_perm = nullptr;   // work order from degrid_plan_sort (nullptr: input order)
+    std::vector<uint32_t> start;  // first tap per work position (from degrid_plan_sort)
+    uint64_t version = 0;         // bumped when tiles or work order change
 };
 
 struct dg_batch_ {
     std::vector<dg_plan> plans;
+    std::vector<uint64_t> plan_versions;
     int32_t grid_dtype = 0, gcf_dtype = 0;
     int32_t device = 0;
     int32_t blocks = 0;
@@ -173,6 +179,7 @@ Problem problem_of(const dg_plan_* p, const void* subgrids, const void* g_uv, co
     pr.uvw = uvw;
     pr.vis = vis;
     pr.grid_out = grid_out;
+    pr.perm = p->d_perm;
     pr.cells_per_sub = (int64_t)d.n_v * d.n_u * d.n_w;
     pr.n_v = d.n_v;
     pr.n_u = d.n_u;
@@ -195,20 +202,26 @@ int32_t blocks_for(int32_t cap, int64_t n_tiles) {
     return (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap, useful));
 }
 
-dg_status device_capacity(int grid_kind, int gcf_kind, int variant, int32_t* device, int32_t* cap) {
+// Resident workgroups on the whole device for every degrid variant and for
+// the adjoint kernel (CU count x occupancy).
+dg_status device_capacity(dg_plan_* p) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     int n_cu = 0;
     e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(CU count)");
-    int fwd = 0, adj = 0;
-    e = degrid_kernel_occupancy(grid_kind, gcf_kind, variant, &fwd);
-    if (e != hipSuccess) return hip_fail(e, "occupancy query (degrid)");
-    e = adjoint_kernel_occupancy(gcf_kind, 0, &adj);
+    for (int v = 0; v < degrid_variant_count(); ++v) {
+        int occ = 0;
+        e = degrid_kernel_occupancy(p->desc.grid_dtype, p->desc.gcf_dtype, v, &occ);
+        if (e != hipSuccess) return hip_fail(e, "occupancy query (degrid)");
+        p->cap[v] = std::max(1, n_cu * std::max(1, occ));
+    }
+    int adj = 0;
+    e = adjoint_kernel_occupancy(p->desc.gcf_dtype, 0, &adj);
     if (e != hipSuccess) return hip_fail(e, "occupancy query (adjoint)");
-    *device = dev;
-    *cap = (int32_t)std::max(1, n_cu * std::max(1, std::min(fwd, adj)));
+    p->cap_adj = std::max(1, n_cu * std::max(1, adj));
+    p->device = dev;
     return DG_OK;
 }
 
@@ -249,16 +262,31 @@ void tune_cache_store(const std::string& key, int32_t n_b, int32_t variant) {
     f << key << " " << n_b << " " << variant << "\n";
 }
 
-// Default tile size when neither the caller nor the tuning cache fixes one.
+// Default tile size and kernel variant when neither the caller nor the tuning
+// cache fixes them.
 constexpr int32_t kDefaultNb = 64;
+constexpr int32_t kDefaultVariant = 2;
+
+// Smallest tile worth staging when tiles are cut to fit the box.
+constexpr int kMinStagedTile = 16;
 
 dg_status rebuild_tiles(dg_plan_* p, int32_t n_b, hipStream_t stream) {
-    std::vector<Tile> tiles = build_tiles(p->n_sub, p->offsets.data(), n_b, 0);
+    const int box = degrid_variant_box_bytes(p->variant);
+    std::vector<Tile> tiles;
+    if (box > 0 && !p->start.empty()) {
+        const int64_t cap = box / (int64_t)(grid_elem_bytes(p->desc.grid_dtype) * kSupportW);
+        tiles = build_tiles_fitted(p->n_sub, p->offsets.data(), p->start.data(), n_b, kSupportUV, cap,
+                                   std::min<int>(kMinStagedTile, n_b), 0);
+    } else {
+        tiles = build_tiles(p->n_sub, p->offsets.data(), n_b, 0);
+    }
     dg_status s = alloc_scratch(p->ds, tiles, stream);
     if (s != DG_OK) return s;
     p->n_b = n_b;
+    p->version++;
     p->q = split_queues(tiles);
-    p->blocks = blocks_for(p->blocks_cap, p->ds.n_tiles);
+    p->blocks = blocks_for(p->cap[p->variant], p->ds.n_tiles);
+    p->blocks_adj = blocks_for(p->cap_adj, p->ds.n_tiles);
     return DG_OK;
 }
 
@@ -289,10 +317,10 @@ dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_o
     p->desc = *d;
     p->n_sub = n_subgrids;
     p->offsets.assign(vis_offsets, vis_offsets + n_subgrids + 1);
-    int32_t n_b = d->n_b, variant = 0;
+    int32_t n_b = d->n_b, variant = kDefaultVariant;
     if (n_b == 0 && !tune_cache_lookup(tune_key(p), &n_b, &variant)) n_b = kDefaultNb;
     p->variant = variant;
-    s = device_capacity(d->grid_dtype, d->gcf_dtype, variant, &p->device, &p->blocks_cap);
+    s = device_capacity(p);
     if (s == DG_OK) s = rebuild_tiles(p, n_b, stream);
     if (s != DG_OK) {
         free_scratch(p->ds);
@@ -332,7 +360,7 @@ dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void*
     if (p->ds.n_tiles == 0) return DG_OK;
     if (!vis || !g_uv || !g_w || !uvw) return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
     const Problem pr = problem_of(p, nullptr, g_uv, g_w, uvw, const_cast<void*>(vis), subgrids_out);
-    hipError_t e = launch_grid_adjoint(params_for(p, pr), p->desc.gcf_dtype, 0, p->blocks, stream);
+    hipError_t e = launch_grid_adjoint(params_for(p, pr), p->desc.gcf_dtype, 0, p->blocks_adj, stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
     p->last_stream = stream;
     p->launched = true;
@@ -363,6 +391,8 @@ dg_status degrid_plan_get_info(dg_plan p, dg_plan_info* info) {
     info->block_threads = kBlockThreads;
     info->n_queues = p->q.n_queues;
     info->device = p->device;
+    info->sorted = p->d_perm ? 1 : 0;
+    info->n_kernels = degrid_variant_count();
     return DG_OK;
 }
 
@@ -410,9 +440,64 @@ dg_status degrid_tune(dg_plan p, const void* subgrids, const void* g_uv, const v
     return DG_OK;
 }
 
+dg_status degrid_plan_sort(dg_plan p, const double* uvw, hipStream_t stream) {
+    if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");
+    const int64_t n = p->offsets.back();
+    if (!uvw) {
+        if (p->d_perm) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p->d_perm);
+            p->d_perm = nullptr;
+            p->start.clear();
+            return rebuild_tiles(p, p->n_b, stream);
+        }
+        return DG_OK;
+    }
+    if (n >= (int64_t(1) << 32)) return fail(DG_ERR_UNSUPPORTED, "work order needs N < 2^32");
+    if (n == 0) return DG_OK;
+    if (fault_injected("alloc")) return fail(DG_ERR_NOMEM, "allocation failure injected (DG_FAULT_INJECT=alloc)");
+    hipError_t e;
+    if (!p->d_perm) {
+        e = hipMalloc(&p->d_perm, sizeof(uint32_t) * (size_t)n);
+        if (e != hipSuccess) { p->d_perm = nullptr; return hip_fail(e, "hipMalloc(work order)"); }
+    }
+    e = sort_visibilities(uvw, p->offsets.data(), p->n_sub, p->d_perm, stream);
+    if (e != hipSuccess) {
+        (void)hipFree(p->d_perm);
+        p->d_perm = nullptr;
+        return hip_fail(e, "sorting the work order");
+    }
+    // first taps in the new order, for cutting tiles that fit the LDS box
+    uint32_t* d_start = nullptr;
+    e = hipMalloc(&d_start, sizeof(uint32_t) * (size_t)n);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(start cells)");
+    const Problem pr = problem_of(p, nullptr, nullptr, nullptr, uvw, nullptr, nullptr);
+    e = launch_start_cells(pr, n, d_start, stream);
+    p->start.resize((size_t)n);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->start.data(), d_start, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(d_start);
+    if (e != hipSuccess) {
+        p->start.clear();
+        return hip_fail(e, "computing start cells");
+    }
+    return rebuild_tiles(p, p->n_b, stream);
+}
+
+dg_status degrid_plan_set_kernel(dg_plan p, int32_t kernel, int32_t n_b, hipStream_t stream) {
+    if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");
+    if (kernel < -1 || kernel >= degrid_variant_count())
+        return fail(DG_ERR_INVALID_ARG, "kernel must be in [-1, %d), got %d", degrid_variant_count(), kernel);
+    if (n_b < 0 || n_b > kMaxNb) return fail(DG_ERR_INVALID_ARG, "n_b must be in [0, %d], got %d", kMaxNb, n_b);
+    if (kernel >= 0) p->variant = kernel;
+    return rebuild_tiles(p, n_b > 0 ? n_b : p->n_b, stream);
+}
+
 dg_status degrid_destroy(dg_plan p) {
     if (!p) return DG_OK;
     (void)hipDeviceSynchronize();
+    if (p->d_perm) (void)hipFree(p->d_perm);
     free_scratch(p->ds);
     delete p;
     return DG_OK;
@@ -434,6 +519,7 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
     dg_batch_* b = new (std::nothrow) dg_batch_();
     if (!b) return fail(DG_ERR_NOMEM, "host allocation of the batch failed");
     b->plans.assign(plans, plans + n);
+    for (int32_t i = 0; i < n; ++i) b->plan_versions.push_back(plans[i]->version);
     b->grid_dtype = plans[0]->desc.grid_dtype;
     b->gcf_dtype = plans[0]->desc.gcf_dtype;
     b->device = plans[0]->device;
@@ -451,7 +537,7 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
     s = alloc_scratch(b->ds, tiles, nullptr);
     if (s != DG_OK) return bail(s);
     b->q = split_queues(tiles);
-    b->blocks = blocks_for(plans[0]->blocks_cap, b->ds.n_tiles);
+    b->blocks = blocks_for(plans[0]->cap[plans[0]->variant], b->ds.n_tiles);
     e = hipMalloc(&b->d_probs, sizeof(Problem) * n);
     if (e != hipSuccess) { b->d_probs = nullptr; return bail(hip_fail(e, "hipMalloc(problem table)")); }
     e = hipHostMalloc(&b->h_probs, sizeof(Problem) * n, hipHostMallocDefault);
@@ -502,6 +588,9 @@ dg_status degrid_batch_execute(dg_batch b, const void* const* args, hipStream_t 
         for (int k = 0; k < 5; ++k)
             if (!args[5 * i + k]) return fail(DG_ERR_INVALID_ARG, "args[%zu] is NULL", 5 * i + k);
     }
+    for (size_t i = 0; i < n; ++i)
+        if (b->plans[i]->version != b->plan_versions[i])
+            return fail(DG_ERR_NOT_READY, "plan %zu changed (sorted or tuned) after the batch was planned", i);
     if (b->ds.n_tiles == 0) return DG_OK;
     const bool same = b->uploaded && std::equal(b->last_args.begin(), b->last_args.end(), args);
     hipError_t e;

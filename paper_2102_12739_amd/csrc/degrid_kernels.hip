@@ -48,6 +48,21 @@ __device__ __forceinline__ int xcc_id() {
 
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Copy of a value that the compiler knows to be the same on every lane (it
+// lives in scalar registers). Used for the per-tile descriptors loaded from
+// memory, so that addresses and buffer resources built from them stay scalar.
+template <class T>
+__device__ __forceinline__ T uniform_copy(const T& x) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized types only");
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, &x, sizeof(T));
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) w[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)w[i]);
+    T y;
+    __builtin_memcpy(&y, w, sizeof(T));
+    return y;
+}
+
 // Orders this wavefront's LDS accesses around a hand-off between its lanes.
 // LDS operations of one wavefront execute in order; this keeps the compiler
 // from moving accesses across the hand-off.
@@ -115,6 +130,8 @@ template <> struct GridTraits<kGridCF16> {   // complex float16
     static constexpr uint32_t kElemBytes = 4;
     static constexpr int kWords = 4;
 };
+// bytes of one (v, u) cell: its 4 w values
+template <int G> constexpr uint32_t kCellBytes = GridTraits<G>::kElemBytes * kSupportW;
 
 template <int G>
 __device__ __forceinline__ void load_w4(__amdgpu_buffer_rsrc_t r, uint32_t off,
@@ -189,7 +206,7 @@ __device__ __forceinline__ float load_gcf(const void* table, int64_t idx) {
 // first tap sits W/2 - 1 cells below the cell. Returns false when the
 // neighbourhood leaves the subgrid or the coordinate is not finite.
 __device__ __forceinline__ bool vis_coords(const Problem& pr, int64_t i, int32_t& cell,
-                                           int32_t& tab, int32_t& ow) {
+                                           int32_t& tab, int32_t& ow, int32_t& x_start, int32_t& y_start) {
     const double* c = pr.uvw + 3 * i;
     const double u = c[0], v = c[1], w = c[2];
     const bool ok = (u >= 3.0) & (u < pr.hi_u) & (v >= 3.0) & (v < pr.hi_v) &
@@ -208,17 +225,10 @@ __device__ __forceinline__ bool vis_coords(const Problem& pr, int64_t i, int32_t
     ow = kw & (os_w - 1);
     cell = (y0 * pr.n_u + x0) * pr.n_w + z0;
     tab = ((ov << pr.log2_os_uv) + ou) * (kSupportUV * kSupportUV);
+    x_start = x0;
+    y_start = y0;
     return true;
 }
-
-// Coordinates of one visibility as staged in LDS for the gather.
-struct VisRec {
-    int32_t cell;   // first-tap cell offset inside the subgrid; -1 if out of range
-    int32_t tab;    // element offset of the 8x8 G_uv block
-    int32_t pad0, pad1;
-    float gw[4];    // G_w[o_w][0..3]; zeros when out of range
-};
-static_assert(sizeof(VisRec) == 32, "VisRec layout");
 
 // Coordinates and the G_w-weighted visibility of one visibility (adjoint).
 struct AdjRec {
@@ -277,11 +287,110 @@ __device__ __forceinline__ void reduce8(float (&p)[8]) {
 // Degrid kernel
 // ---------------------------------------------------------------------------
 
-template <int G, int F>
+__device__ __forceinline__ int wave_min(int x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x = min(x, __shfl_xor(x, m));
+    return x;
+}
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x = max(x, __shfl_xor(x, m));
+    return x;
+}
+
+// Scalar-cache view of a table: loads through it with a wave-uniform address
+// become scalar loads (the tables are read-only for the whole launch).
+typedef const __attribute__((address_space(4))) float* ConstF32Ptr;
+typedef const __attribute__((address_space(4))) uint32_t* ConstU32Ptr;
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// G_w[o_w][0..3] as four floats, read through the scalar cache.
+template <int F>
+__device__ __forceinline__ float4 load_gw_row(uint64_t g_w, int ow) {
+    if constexpr (F == kGcfF32) {
+        const ConstF32Ptr p = (ConstF32Ptr)g_w + ow * kSupportW;
+        return make_float4(p[0], p[1], p[2], p[3]);
+    } else {
+        const ConstU32Ptr p = (ConstU32Ptr)g_w + ow * (kSupportW / 2);
+        const __half2 a = __builtin_bit_cast(__half2, p[0]);
+        const __half2 b = __builtin_bit_cast(__half2, p[1]);
+        return make_float4(__low2float(a), __high2float(a), __low2float(b), __high2float(b));
+    }
+}
+
+// LDS box of one wavefront: a copy of the cells of a tile's bounding box,
+// row-major, split into two planes of 16 bytes per cell (w 0-1 and w 2-3 of
+// complex64; the whole cell for 16-bit storage) so that eight lanes reading
+// neighbouring cells touch one contiguous 128-byte span of banks.
+template <int G, int BOX>
+__device__ __forceinline__ void lds_w4(const char* box, uint32_t off, uint32_t (&raw)[GridTraits<G>::kWords]) {
+    const uint4 a = *reinterpret_cast<const uint4*>(box + off);
+    raw[0] = a.x; raw[1] = a.y; raw[2] = a.z; raw[3] = a.w;
+    if constexpr (G == kGridC64) {
+        const uint4 b = *reinterpret_cast<const uint4*>(box + BOX / 2 + off);
+        raw[4] = b.x; raw[5] = b.y; raw[6] = b.z; raw[7] = b.w;
+    }
+}
+
+// Weighted sums of one tile's visibilities, eight at a time. Lane j holds the
+// coordinate-stage results of visibility j: a_off (byte offset of its first
+// tap in the LDS box, or in the subgrid; kOutOfRange in the subgrid when out
+// of range), g_off (byte offset of its G_uv block, kOutOfRange when out of
+// range) and ow (its G_w row); v_readlane hands them to the whole wavefront.
+// STAGED selects the LDS box or the subgrid in HBM (through the caches).
+template <int G, int F, int BOX, bool STAGED>
+__device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, int g_off, int ow,
+                                            __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rg,
+                                            uint64_t g_w, uint32_t lane_a, uint32_t lane_g,
+                                            const char* box) {
+    using GT = GridTraits<G>;
+    const int lane = lane_id();
+    for (int g0 = 0; g0 < count; g0 += 8) {
+        uint32_t raw[8][GT::kWords];
+        float guv[8];
+        float4 gw[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int j = g0 + k;   // lanes >= count hold out-of-range records
+            const uint32_t aj = (uint32_t)__builtin_amdgcn_readlane(a_off, j);
+            const uint32_t gj = (uint32_t)__builtin_amdgcn_readlane(g_off, j);
+            gw[k] = load_gw_row<F>(g_w, __builtin_amdgcn_readlane(ow, j));
+            guv[k] = load_gcf_rsrc<F>(rg, gj + lane_g);
+            if constexpr (STAGED) {
+                lds_w4<G, BOX>(box, lane_a + aj, raw[k]);
+            } else {
+                load_w4<G>(ra, lane_a + aj, raw[k]);
+            }
+        }
+        float pre[8], pim[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            float re[4], im[4];
+            widen_w4<G>(raw[k], re, im);
+            const float sr = gw[k].x * re[0] + gw[k].y * re[1] + gw[k].z * re[2] + gw[k].w * re[3];
+            const float si = gw[k].x * im[0] + gw[k].y * im[1] + gw[k].z * im[2] + gw[k].w * im[3];
+            pre[k] = guv[k] * sr;
+            pim[k] = guv[k] * si;
+        }
+        reduce8(pre);
+        reduce8(pim);
+        if ((lane & 7) == 0) out[g0 + (lane >> 3)] = make_float2(pre[0], pim[0]);
+    }
+}
+
+// BOX: bytes of LDS per wavefront for the staged copy of a tile's cells
+// (0: always gather through the caches).
+template <int G, int F, int BOX>
 __global__ __launch_bounds__(kBlockThreads) void degrid_kernel(LaunchParams P) {
     using GT = GridTraits<G>;
-    __shared__ VisRec s_rec[kWavesPerBlock][kMaxNb];
+    constexpr int kBoxChunks = BOX > 0 ? BOX / 16 : 1;
     __shared__ float2 s_out[kWavesPerBlock][kMaxNb];
+    __shared__ uint4 s_box[kWavesPerBlock][kBoxChunks];
 
     const int lane = lane_id();
     const int wv = (int)(threadIdx.x / kWave);
@@ -290,73 +399,87 @@ __global__ __launch_bounds__(kBlockThreads) void degrid_kernel(LaunchParams P) {
 
     int t = pop_tile(P.q, P.ctl, st);
     while (t >= 0) {
-        const Tile tile = P.tiles[t];
+        const Tile tile = uniform_copy(P.tiles[t]);
         const int t_next = pop_tile(P.q, P.ctl, st);
-        const Problem pr = P.probs ? P.probs[tile.problem] : P.prob;
+        const Problem pr = P.probs ? uniform_copy(P.probs[tile.problem]) : P.prob;
         const int count = tile.count;
 
-        // Coordinate stage: lane j handles visibility begin + j.
-        {
-            VisRec r;
-            r.cell = -1;
-            r.tab = 0;
-            r.pad0 = r.pad1 = 0;
-            r.gw[0] = r.gw[1] = r.gw[2] = r.gw[3] = 0.0f;
-            bool in_range = false;
-            if (lane < count) {
-                int32_t ow = 0;
-                in_range = vis_coords(pr, tile.begin + lane, r.cell, r.tab, ow);
-                if (in_range) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) r.gw[k] = load_gcf<F>(pr.g_w, ow * kSupportW + k);
-                } else {
-                    r.cell = -1;
-                    r.tab = 0;
-                }
-            }
-            wave_oob += (uint32_t)__popcll(__ballot(lane < count && !in_range));
-            s_rec[wv][lane] = r;
+        // Coordinate stage: lane j handles the j-th visibility of the tile.
+        int64_t my_vis = 0;
+        bool in_range = false;
+        int x0 = 0, y0 = 0, cell = 0, tab = 0, ow = 0;
+        if (lane < count) {
+            my_vis = pr.perm ? (int64_t)pr.perm[tile.begin + lane] : tile.begin + lane;
+            in_range = vis_coords(pr, my_vis, cell, tab, ow, x0, y0);
+            if (!in_range) ow = 0;
         }
-        wave_lds_sync();
+        wave_oob += (uint32_t)__popcll(__ballot(lane < count && !in_range));
+        const int g_off = in_range ? tab * (int)GcfTraits<F>::kBytes : (int)kOutOfRange;
 
-        // Gather: lane = (t_v, t_u); 4 w values per lane.
         const char* sub_base = static_cast<const char*>(pr.subgrids) + (int64_t)tile.sub * pr.sub_bytes;
         const __amdgpu_buffer_rsrc_t ra = make_rsrc(sub_base, pr.sub_bytes);
         const __amdgpu_buffer_rsrc_t rg = make_rsrc(pr.g_uv, pr.guv_bytes);
-        const uint32_t lane_a = (uint32_t)(((lane >> 3) * pr.n_u + (lane & 7)) * pr.n_w) * GT::kElemBytes;
+        const uint64_t g_w = uniform_u64((uint64_t)pr.g_w);
         const uint32_t lane_g = (uint32_t)lane * GcfTraits<F>::kBytes;
 
-        for (int g0 = 0; g0 < count; g0 += 8) {
-            uint32_t raw[8][GT::kWords];
-            float guv[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int j = g0 + k;
-                const int cell = uniform(s_rec[wv][j].cell);
-                const int tab = uniform(s_rec[wv][j].tab);
-                const bool live = (j < count) & (cell >= 0);
-                const uint32_t oa = live ? (uint32_t)cell * GT::kElemBytes + lane_a : kOutOfRange;
-                const uint32_t og = live ? (uint32_t)tab * GcfTraits<F>::kBytes + lane_g : kOutOfRange;
-                load_w4<G>(ra, oa, raw[k]);
-                guv[k] = load_gcf_rsrc<F>(rg, og);
+        bool staged = false;
+        int bx0 = 0, by0 = 0, bw = 0, bh = 0;
+        if constexpr (BOX > 0) {
+            // bounding box of the tile's neighbourhoods
+            bx0 = uniform(wave_min(in_range ? x0 : 0x7FFFFFFF));
+            by0 = uniform(wave_min(in_range ? y0 : 0x7FFFFFFF));
+            const int bx1 = uniform(wave_max(in_range ? x0 : -1));
+            const int by1 = uniform(wave_max(in_range ? y0 : -1));
+            if (bx1 >= 0) {
+                bw = bx1 - bx0 + kSupportUV;
+                bh = by1 - by0 + kSupportUV;
+                staged = (uint32_t)(bw * bh) * kCellBytes<G> <= (uint32_t)BOX;
             }
-            float pre[8], pim[8];
+        }
+        if (staged) {
+            // Copy the box row by row: rc 16-byte chunks per row, one chunk
+            // per lane and step, four steps in flight.
+            constexpr int kHalves = (int)(kCellBytes<G> / 16);   // 2 for complex64, else 1
+            const int rc = bw * kHalves;
+            const int total = rc * bh;
+            const float inv_rc = 1.0f / (float)rc;
+            const uint32_t row_stride = (uint32_t)pr.n_u * pr.n_w * GT::kElemBytes;
+            const uint32_t box_origin = ((uint32_t)by0 * pr.n_u + bx0) * pr.n_w * GT::kElemBytes;
+            char* box = reinterpret_cast<char*>(s_box[wv]);
+            for (int c0 = 0; c0 < total; c0 += 4 * kWave) {
+                uint4 v[4];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const float4 gw = *reinterpret_cast<const float4*>(s_rec[wv][g0 + k].gw);
-                float re[4], im[4];
-                widen_w4<G>(raw[k], re, im);
-                const float sr = gw.x * re[0] + gw.y * re[1] + gw.z * re[2] + gw.w * re[3];
-                const float si = gw.x * im[0] + gw.y * im[1] + gw.z * im[2] + gw.w * im[3];
-                pre[k] = guv[k] * sr;
-                pim[k] = guv[k] * si;
+                for (int k = 0; k < 4; ++k) {
+                    const int c = c0 + k * kWave + lane;
+                    const int row = (int)(((float)c + 0.5f) * inv_rc);
+                    const int col = c - row * rc;
+                    const uint32_t off = c < total ? box_origin + (uint32_t)row * row_stride + (uint32_t)col * 16u
+                                                   : kOutOfRange;
+                    v[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(ra, off, 0, 0));
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = c0 + k * kWave + lane;
+                    // chunk c is half (c mod 2) of cell c / 2 for complex64
+                    const uint32_t dst = kHalves == 2 ? (uint32_t)(c & 1) * (BOX / 2) + (uint32_t)(c >> 1) * 16u
+                                                      : (uint32_t)c * 16u;
+                    if (c < total) *reinterpret_cast<uint4*>(box + dst) = v[k];
+                }
             }
-            reduce8(pre);
-            reduce8(pim);
-            if ((lane & 7) == 0) s_out[wv][g0 + (lane >> 3)] = make_float2(pre[0], pim[0]);
+            wave_lds_sync();
+            // out-of-range visibilities read cell (0, 0) of the box; their
+            // weight is zero and their output is overwritten with zero
+            const int a_off = in_range ? ((y0 - by0) * bw + (x0 - bx0)) * 16 : 0;
+            const uint32_t lane_box = ((uint32_t)(lane >> 3) * bw + (lane & 7)) * 16u;
+            gather_tile<G, F, BOX, true>(s_out[wv], count, a_off, g_off, ow, ra, rg, g_w, lane_box, lane_g, box);
+        } else {
+            const int a_off = in_range ? cell * (int)GT::kElemBytes : (int)kOutOfRange;
+            const uint32_t lane_a = (uint32_t)(((lane >> 3) * pr.n_u + (lane & 7)) * pr.n_w) * GT::kElemBytes;
+            gather_tile<G, F, BOX, false>(s_out[wv], count, a_off, g_off, ow, ra, rg, g_w, lane_a, lane_g, nullptr);
         }
         wave_lds_sync();
-        if (lane < count) static_cast<float2*>(pr.vis)[tile.begin + lane] = s_out[wv][lane];
+        if (lane < count)
+            static_cast<float2*>(pr.vis)[my_vis] = in_range ? s_out[wv][lane] : make_float2(0.f, 0.f);
         wave_lds_sync();
         t = t_next;
     }
@@ -378,9 +501,9 @@ __global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParam
 
     int t = pop_tile(P.q, P.ctl, st);
     while (t >= 0) {
-        const Tile tile = P.tiles[t];
+        const Tile tile = uniform_copy(P.tiles[t]);
         const int t_next = pop_tile(P.q, P.ctl, st);
-        const Problem pr = P.probs ? P.probs[tile.problem] : P.prob;
+        const Problem pr = P.probs ? uniform_copy(P.probs[tile.problem]) : P.prob;
         const int count = tile.count;
 
         {
@@ -392,10 +515,11 @@ __global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParam
             for (int k = 0; k < 8; ++k) r.c[k] = 0.0f;
             bool in_range = false;
             if (lane < count) {
-                int32_t ow = 0;
-                in_range = vis_coords(pr, tile.begin + lane, r.cell, r.tab, ow);
+                const int64_t i = pr.perm ? (int64_t)pr.perm[tile.begin + lane] : tile.begin + lane;
+                int32_t ow = 0, x0 = 0, y0 = 0;
+                in_range = vis_coords(pr, i, r.cell, r.tab, ow, x0, y0);
                 if (in_range) {
-                    const float2 vv = static_cast<const float2*>(pr.vis)[tile.begin + lane];
+                    const float2 vv = static_cast<const float2*>(pr.vis)[i];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const float gw = load_gcf<F>(pr.g_w, ow * kSupportW + k);
@@ -444,51 +568,92 @@ __global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParam
     finish_launch(P.ctl, wave_oob);
 }
 
+// First tap (y0 << 16 | x0) of the visibility at each position of the work
+// order, or kNoStart when it is out of range: plan-time input for cutting
+// tiles whose cells fit a staging box.
+__global__ void start_cells_kernel(Problem pr, int64_t n, uint32_t* start) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int64_t i = pr.perm ? (int64_t)pr.perm[p] : p;
+    int32_t cell = 0, tab = 0, ow = 0, x0 = 0, y0 = 0;
+    start[p] = vis_coords(pr, i, cell, tab, ow, x0, y0) ? ((uint32_t)y0 << 16) | (uint32_t)x0 : kNoStart;
+}
+
 __global__ void zero_kernel(float4* p, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
         p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-template <int G, int F>
+// Kernel variants: the LDS box per wavefront (bytes); 0 gathers through the
+// caches only.
+constexpr int kBoxVariants[] = {0, 8192, 16384, 24576, 32768};
+constexpr int kNumVariants = sizeof(kBoxVariants) / sizeof(kBoxVariants[0]);
+
+template <int G, int F, int BOX>
 hipError_t launch_degrid_t(const LaunchParams& p, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((degrid_kernel<G, F>), dim3(blocks), dim3(kBlockThreads), 0, s, p);
+    hipLaunchKernelGGL((degrid_kernel<G, F, BOX>), dim3(blocks), dim3(kBlockThreads), 0, s, p);
     return hipGetLastError();
 }
 
-template <int G, int F>
+template <int G, int F, int BOX>
 hipError_t occ_degrid_t(int* n) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, degrid_kernel<G, F>, kBlockThreads, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, degrid_kernel<G, F, BOX>, kBlockThreads, 0);
+}
+
+template <int G, int F>
+hipError_t launch_degrid_v(const LaunchParams& p, int variant, int blocks, hipStream_t s) {
+    switch (variant) {
+        case 0: return launch_degrid_t<G, F, kBoxVariants[0]>(p, blocks, s);
+        case 1: return launch_degrid_t<G, F, kBoxVariants[1]>(p, blocks, s);
+        case 2: return launch_degrid_t<G, F, kBoxVariants[2]>(p, blocks, s);
+        case 3: return launch_degrid_t<G, F, kBoxVariants[3]>(p, blocks, s);
+        case 4: return launch_degrid_t<G, F, kBoxVariants[4]>(p, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int G, int F>
+hipError_t occ_degrid_v(int variant, int* n) {
+    switch (variant) {
+        case 0: return occ_degrid_t<G, F, kBoxVariants[0]>(n);
+        case 1: return occ_degrid_t<G, F, kBoxVariants[1]>(n);
+        case 2: return occ_degrid_t<G, F, kBoxVariants[2]>(n);
+        case 3: return occ_degrid_t<G, F, kBoxVariants[3]>(n);
+        case 4: return occ_degrid_t<G, F, kBoxVariants[4]>(n);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-int degrid_variant_count() { return 1; }
+int degrid_variant_count() { return kNumVariants; }
 int adjoint_variant_count() { return 1; }
+int degrid_variant_box_bytes(int variant) {
+    return (variant >= 0 && variant < kNumVariants) ? kBoxVariants[variant] : -1;
+}
 
 hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int variant,
                          int blocks, hipStream_t stream) {
-    (void)variant;
     switch (grid_kind * 2 + gcf_kind) {
-        case kGridC64 * 2 + kGcfF32: return launch_degrid_t<kGridC64, kGcfF32>(p, blocks, stream);
-        case kGridC64 * 2 + kGcfF16: return launch_degrid_t<kGridC64, kGcfF16>(p, blocks, stream);
-        case kGridCBF16 * 2 + kGcfF32: return launch_degrid_t<kGridCBF16, kGcfF32>(p, blocks, stream);
-        case kGridCBF16 * 2 + kGcfF16: return launch_degrid_t<kGridCBF16, kGcfF16>(p, blocks, stream);
-        case kGridCF16 * 2 + kGcfF32: return launch_degrid_t<kGridCF16, kGcfF32>(p, blocks, stream);
-        case kGridCF16 * 2 + kGcfF16: return launch_degrid_t<kGridCF16, kGcfF16>(p, blocks, stream);
+        case kGridC64 * 2 + kGcfF32: return launch_degrid_v<kGridC64, kGcfF32>(p, variant, blocks, stream);
+        case kGridC64 * 2 + kGcfF16: return launch_degrid_v<kGridC64, kGcfF16>(p, variant, blocks, stream);
+        case kGridCBF16 * 2 + kGcfF32: return launch_degrid_v<kGridCBF16, kGcfF32>(p, variant, blocks, stream);
+        case kGridCBF16 * 2 + kGcfF16: return launch_degrid_v<kGridCBF16, kGcfF16>(p, variant, blocks, stream);
+        case kGridCF16 * 2 + kGcfF32: return launch_degrid_v<kGridCF16, kGcfF32>(p, variant, blocks, stream);
+        case kGridCF16 * 2 + kGcfF16: return launch_degrid_v<kGridCF16, kGcfF16>(p, variant, blocks, stream);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t degrid_kernel_occupancy(int grid_kind, int gcf_kind, int variant, int* n) {
-    (void)variant;
     switch (grid_kind * 2 + gcf_kind) {
-        case kGridC64 * 2 + kGcfF32: return occ_degrid_t<kGridC64, kGcfF32>(n);
-        case kGridC64 * 2 + kGcfF16: return occ_degrid_t<kGridC64, kGcfF16>(n);
-        case kGridCBF16 * 2 + kGcfF32: return occ_degrid_t<kGridCBF16, kGcfF32>(n);
-        case kGridCBF16 * 2 + kGcfF16: return occ_degrid_t<kGridCBF16, kGcfF16>(n);
-        case kGridCF16 * 2 + kGcfF32: return occ_degrid_t<kGridCF16, kGcfF32>(n);
-        case kGridCF16 * 2 + kGcfF16: return occ_degrid_t<kGridCF16, kGcfF16>(n);
+        case kGridC64 * 2 + kGcfF32: return occ_degrid_v<kGridC64, kGcfF32>(variant, n);
+        case kGridC64 * 2 + kGcfF16: return occ_degrid_v<kGridC64, kGcfF16>(variant, n);
+        case kGridCBF16 * 2 + kGcfF32: return occ_degrid_v<kGridCBF16, kGcfF32>(variant, n);
+        case kGridCBF16 * 2 + kGcfF16: return occ_degrid_v<kGridCBF16, kGcfF16>(variant, n);
+        case kGridCF16 * 2 + kGcfF32: return occ_degrid_v<kGridCF16, kGcfF32>(variant, n);
+        case kGridCF16 * 2 + kGcfF16: return occ_degrid_v<kGridCF16, kGcfF16>(variant, n);
         default: return hipErrorInvalidValue;
     }
 }
@@ -510,6 +675,13 @@ hipError_t adjoint_kernel_occupancy(int gcf_kind, int variant, int* n) {
     if (gcf_kind == kGcfF32)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, grid_adjoint_kernel<kGcfF32>, kBlockThreads, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, grid_adjoint_kernel<kGcfF16>, kBlockThreads, 0);
+}
+
+hipError_t launch_start_cells(const Problem& pr, int64_t n, uint32_t* start, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(start_cells_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, pr, n, start);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t stream) {

@@ -28,6 +28,7 @@ struct Problem {
     const double* uvw;      // [N][3]
     void* vis;              // complex float32 [N]: degrid output / adjoint input
     void* grid_out;         // complex float32 [S][n_v][n_u][n_w]: adjoint output
+    const uint32_t* perm;   // work order: tile position -> visibility index; nullptr = identity
     int64_t cells_per_sub;  // n_v * n_u * n_w
     int32_t n_v, n_u, n_w;
     int32_t log2_os_uv, log2_os_w;
@@ -66,9 +67,21 @@ hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int
 hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant, int blocks,
                                hipStream_t stream);
 hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t stream);
+// start[p] = first tap (y0 << 16 | x0) of the visibility at work position p
+// (through pr.perm), or kNoStart when out of range.
+hipError_t launch_start_cells(const Problem& pr, int64_t n, uint32_t* start, hipStream_t stream);
+
+// Stable sort of each subgrid's visibilities by the Morton code of the cell
+// holding (u, v) (defined in plan_sort.hip). Writes perm[n_vis]: the
+// visibility index at each position of the new work order. Allocates and
+// frees its own temporary buffers; synchronises 'stream'.
+hipError_t sort_visibilities(const double* uvw, const int64_t* offsets_host, int64_t n_sub,
+                             uint32_t* perm, hipStream_t stream);
 hipError_t degrid_kernel_occupancy(int grid_kind, int gcf_kind, int variant, int* blocks_per_cu);
 hipError_t adjoint_kernel_occupancy(int gcf_kind, int variant, int* blocks_per_cu);
 int degrid_variant_count();
 int adjoint_variant_count();
+int degrid_variant_box_bytes(int variant);   // LDS staging bytes per wavefront (0: none)
+constexpr int kMaxVariants = 8;
 
 }  // namespace dg

@@ -21,6 +21,43 @@ std::vector<Tile> build_tiles(int64_t n_sub, const int64_t* off, int nb, uint16_
     return tiles;
 }
 
+std::vector<Tile> build_tiles_fitted(int64_t n_sub, const int64_t* off, const uint32_t* start, int nb,
+                                     int support, int64_t cap_cells, int min_fit, uint16_t problem) {
+    std::vector<Tile> tiles;
+    for (int64_t s = 0; s < n_sub; ++s) {
+        int64_t i = off[s];
+        const int64_t e = off[s + 1];
+        while (i < e) {
+            // longest prefix (at most nb) whose box fits
+            int32_t xl = 0, xh = -1, yl = 0, yh = -1;   // empty box
+            int64_t k = 0;
+            while (k < nb && i + k < e) {
+                const uint32_t st = start[i + k];
+                if (st != kNoStart) {
+                    const int32_t x = (int32_t)(st & 0xFFFFu), y = (int32_t)(st >> 16);
+                    const int32_t nxl = xh < xl ? x : std::min(xl, x), nxh = xh < xl ? x : std::max(xh, x);
+                    const int32_t nyl = yh < yl ? y : std::min(yl, y), nyh = yh < yl ? y : std::max(yh, y);
+                    const int64_t area = (int64_t)(nxh - nxl + support) * (nyh - nyl + support);
+                    if (area > cap_cells) break;
+                    xl = nxl; xh = nxh; yl = nyl; yh = nyh;
+                }
+                ++k;
+            }
+            int64_t n = k;
+            if (k < min_fit && i + k < e) n = std::min<int64_t>(nb, e - i);
+            if (n < 1) n = 1;
+            Tile t;
+            t.begin = i;
+            t.sub = (int32_t)s;
+            t.count = (uint16_t)n;
+            t.problem = problem;
+            tiles.push_back(t);
+            i += n;
+        }
+    }
+    return tiles;
+}
+
 QueueSpec split_queues(const std::vector<Tile>& tiles) {
     QueueSpec q{};
     const int64_t n_tiles = (int64_t)tiles.size();

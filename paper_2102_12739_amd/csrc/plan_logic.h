@@ -36,6 +36,20 @@ struct QueueSpec {
 // into tiles of at most nb consecutive visibilities, in subgrid order.
 std::vector<Tile> build_tiles(int64_t n_sub, const int64_t* off, int nb, uint16_t problem);
 
+// Marker of a visibility whose neighbourhood leaves its subgrid.
+constexpr uint32_t kNoStart = 0xFFFFFFFFu;
+
+// Like build_tiles, but cut where a tile's cells stop fitting a staging box:
+// start[p] is the first tap (y0 << 16 | x0) of the visibility at position p
+// of the work order, or kNoStart. A tile grows while the bounding box of its
+// neighbourhoods ((x1 - x0 + W) x (y1 - y0 + W) cells, W = support) holds at
+// most cap_cells cells and it has fewer than nb visibilities. If fewer than
+// min_fit visibilities fit, the tile takes nb visibilities anyway (it will
+// be gathered without staging) so that sparse regions do not become many
+// tiny tiles. Out-of-range visibilities never enlarge a box.
+std::vector<Tile> build_tiles_fitted(int64_t n_sub, const int64_t* off, const uint32_t* start, int nb,
+                                     int support, int64_t cap_cells, int min_fit, uint16_t problem);
+
 // Split a tile list into up to kMaxQueues contiguous queues holding about
 // equal numbers of visibilities (empty queues only when there are fewer
 // tiles than queues).

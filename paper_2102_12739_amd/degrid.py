@@ -52,7 +52,8 @@ class DgDesc(ctypes.Structure):
 class DgPlanInfo(ctypes.Structure):
     _fields_ = [("n_subgrids", ctypes.c_int64), ("n_vis", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
                 ("n_b", ctypes.c_int32), ("kernel", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("block_threads", ctypes.c_int32), ("n_queues", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("block_threads", ctypes.c_int32), ("n_queues", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("sorted", ctypes.c_int32), ("n_kernels", ctypes.c_int32)]
 
 
 def library_path() -> str:
@@ -76,6 +77,8 @@ def lib():
         "grid_adjoint": ([vp, vp, vp, vp, vp, vp, i32, vp], i32),
         "degrid_oob_count": ([vp, ctypes.POINTER(ctypes.c_int64)], i32),
         "degrid_plan_get_info": ([vp, ctypes.POINTER(DgPlanInfo)], i32),
+        "degrid_plan_sort": ([vp, vp, vp], i32),
+        "degrid_plan_set_kernel": ([vp, i32, i32, vp], i32),
         "degrid_tune": ([vp, vp, vp, vp, vp, vp, vp], i32),
         "degrid_destroy": ([vp], i32),
         "degrid_batch_plan": ([ctypes.POINTER(vp), i32, ctypes.POINTER(vp)], i32),
@@ -210,6 +213,22 @@ class Plan:
         po = _ptr(out, "out", torch.complex64, (self.n_vis,))
         _check(lib().degrid_tune(self._handle, ps, pg, pw, pu, po, _stream_handle(stream)), "degrid_tune")
         return self.info()
+
+    def sort(self, uvw=None, stream=None):
+        """Order the work by subgrid position (Z-order of the cell holding (u, v)).
+
+        Outputs stay in input order and unchanged; later calls are faster when
+        they use these same coordinates. ``uvw=None`` restores input order.
+        """
+        pu = self._check_uvw(uvw) if uvw is not None else None
+        _check(lib().degrid_plan_sort(self._handle, pu, _stream_handle(stream)), "degrid_plan_sort")
+        return self
+
+    def set_kernel(self, kernel: int = -1, n_b: int = 0, stream=None):
+        """Pick the gather kernel variant and/or tile size by hand (-1 / 0 keep)."""
+        _check(lib().degrid_plan_set_kernel(self._handle, int(kernel), int(n_b), _stream_handle(stream)),
+               "degrid_plan_set_kernel")
+        return self
 
     def oob_count(self) -> int:
         c = ctypes.c_int64()

@@ -1,19 +1,19 @@
 // Property checks of the host work decomposition, built with g++ (no HIP).
-// Prints one JSON object per case; the pytest wrapper checks the properties.
+// Prints the tiles and queues as JSON; the pytest wrapper checks properties.
+//   plan_logic_check <nb> <count>...                    fixed-size tiles
+//   plan_logic_check fitted <nb> <cap> <min_fit> <file> tiles cut to fit a box;
+//       <file>: line 1 = per-subgrid counts, line 2 = start word per visibility
 #include "plan_logic.h"
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <vector>
 
-int main(int argc, char** argv) {
-    // argv: nb followed by per-subgrid counts
-    if (argc < 2) return 2;
-    const int nb = std::atoi(argv[1]);
-    std::vector<int64_t> off(1, 0);
-    for (int i = 2; i < argc; ++i) off.push_back(off.back() + std::atoll(argv[i]));
-    const int64_t n_sub = (int64_t)off.size() - 1;
-    std::vector<dg::Tile> tiles = dg::build_tiles(n_sub, off.data(), nb, 3);
+static void print(const std::vector<dg::Tile>& tiles) {
     dg::QueueSpec q = dg::split_queues(tiles);
     std::printf("{\"tiles\": [");
     for (size_t i = 0; i < tiles.size(); ++i)
@@ -24,5 +24,33 @@ int main(int argc, char** argv) {
     std::printf("], \"end\": [");
     for (int i = 0; i < q.n_queues; ++i) std::printf("%s%d", i ? ", " : "", q.end[i]);
     std::printf("]}\n");
+}
+
+int main(int argc, char** argv) {
+    if (argc < 2) return 2;
+    if (std::strcmp(argv[1], "fitted") == 0) {
+        if (argc != 6) return 2;
+        const int nb = std::atoi(argv[2]);
+        const long long cap = std::atoll(argv[3]);
+        const int min_fit = std::atoi(argv[4]);
+        std::ifstream f(argv[5]);
+        std::string l1, l2;
+        std::getline(f, l1);
+        std::getline(f, l2);
+        std::vector<int64_t> off(1, 0);
+        std::istringstream c(l1), st(l2);
+        long long x;
+        while (c >> x) off.push_back(off.back() + x);
+        std::vector<uint32_t> start;
+        unsigned long long w;
+        while (st >> w) start.push_back((uint32_t)w);
+        if ((int64_t)start.size() != off.back()) return 3;
+        print(dg::build_tiles_fitted((int64_t)off.size() - 1, off.data(), start.data(), nb, 8, cap, min_fit, 3));
+        return 0;
+    }
+    const int nb = std::atoi(argv[1]);
+    std::vector<int64_t> off(1, 0);
+    for (int i = 2; i < argc; ++i) off.push_back(off.back() + std::atoll(argv[i]));
+    print(dg::build_tiles((int64_t)off.size() - 1, off.data(), nb, 3));
     return 0;
 }

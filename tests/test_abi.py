@@ -55,7 +55,8 @@ def test_struct_layout_matches_ctypes(tmp_path):
     assert got["dg_desc"] == [ctypes.sizeof(DgDesc), DgDesc.os_uv.offset, DgDesc.grid_dtype.offset,
                               DgDesc.n_b.offset, DgDesc.flags.offset, DgDesc.support_w.offset]
     assert got["dg_plan_info"] == [ctypes.sizeof(DgPlanInfo), DgPlanInfo.n_tiles.offset, DgPlanInfo.n_b.offset,
-                                   DgPlanInfo.n_queues.offset, DgPlanInfo.device.offset]
+                                   DgPlanInfo.n_queues.offset, DgPlanInfo.device.offset, DgPlanInfo.sorted.offset,
+                                   DgPlanInfo.n_kernels.offset]
 
 
 def test_status_strings_and_version(dg):
@@ -111,6 +112,7 @@ def test_null_arguments(dg):
     assert L.degrid_destroy(None) == 0
     assert L.degrid_batch_destroy(None) == 0
     assert L.degrid_batch_plan(None, 0, None) == 1
+    assert L.degrid_plan_sort(None, None, None) == 1
 
 
 def test_plan_without_device_reports_hip_error(dg):
@@ -188,3 +190,64 @@ def test_queues_partition_the_tile_list_and_balance_visibilities(plan_logic, nb,
         per_q = [vis[begin[q]:end[q]].sum() for q in range(nq)]
         share = vis.sum() / nq
         assert max(per_q) <= share + nb and min(per_q) >= share - nb
+
+
+def _fitted(plan_logic_exe, tmp_path, nb, cap, min_fit, counts, starts):
+    f = tmp_path / "starts.txt"
+    f.write_text(" ".join(map(str, counts)) + "\n" + " ".join(map(str, starts)) + "\n")
+    r = subprocess.run([plan_logic_exe, "fitted", str(nb), str(cap), str(min_fit), str(f)],
+                       capture_output=True, text=True, check=True)
+    return json.loads(r.stdout)
+
+
+@pytest.fixture(scope="module")
+def plan_logic_exe(tmp_path_factory):
+    exe = tmp_path_factory.mktemp("plf") / "plan_logic_check"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-I", CSRC, "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", os.path.join(ROOT, "tests", "cpp", "plan_logic_check.cpp"),
+                    os.path.join(CSRC, "plan_logic.cpp"), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+@pytest.mark.parametrize("seed,cap,min_fit", [(0, 512, 16), (1, 256, 8), (2, 1024, 16), (3, 64, 4)])
+def test_fitted_tiles_cover_fit_the_box_and_are_greedy(plan_logic_exe, tmp_path, seed, cap, min_fit):
+    rng = np.random.default_rng(seed)
+    nb, no_start = 64, 0xFFFFFFFF
+    counts = [int(c) for c in rng.integers(0, 700, 6)] + [0, 1, 65]
+    starts = []
+    for c in counts:
+        # clustered walk of start cells plus some out-of-range entries
+        x, y = rng.integers(0, 500, 2)
+        for _ in range(c):
+            x = int(np.clip(x + rng.integers(-3, 4), 0, 504))
+            y = int(np.clip(y + rng.integers(-3, 4), 0, 504))
+            starts.append(no_start if rng.random() < 0.05 else (y << 16) | x)
+    out = _fitted(plan_logic_exe, tmp_path, nb, cap, min_fit, counts, starts)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    covered = np.zeros(int(off[-1]), dtype=np.int64)
+
+    def area(lo, hi):
+        xs = [s & 0xFFFF for s in starts[lo:hi] if s != no_start]
+        ys = [s >> 16 for s in starts[lo:hi] if s != no_start]
+        if not xs:
+            return 0
+        return (max(xs) - min(xs) + 8) * (max(ys) - min(ys) + 8)
+
+    for begin, sub, count, problem in out["tiles"]:
+        assert problem == 3 and 1 <= count <= nb
+        assert off[sub] <= begin and begin + count <= off[sub + 1]
+        covered[begin:begin + count] += 1
+        end_of_sub = begin + count == off[sub + 1]
+        if area(begin, begin + count) <= cap:
+            # a fitting tile stops only at nb, at its subgrid's end, or where
+            # one more visibility would not fit
+            assert count == nb or end_of_sub or area(begin, begin + count + 1) > cap
+        else:
+            # a tile that does not fit is a full-size fallback: fewer than
+            # min_fit visibilities fit at its start
+            assert count == min(nb, off[sub + 1] - begin)
+            k = 1
+            while k < count and area(begin, begin + k + 1) <= cap:
+                k += 1
+            assert k < min_fit
+    assert np.all(covered == 1)

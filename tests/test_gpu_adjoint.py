@@ -88,3 +88,14 @@ def test_autograd_backward_matches_oracle_gradient_and_finite_differences():
             g = grad.reshape(-1)[j]
             want = g.real if unit == 1.0 else g.imag
             assert abs(dl - want) <= 1e-4 * max(1.0, abs(want)), (j, unit, dl, want)
+
+
+def test_adjoint_with_sorted_work_order_matches_oracle():
+    p = wl.make_problem("adj-sorted", [5000, 3000, 0, 4000], seed=25, kind="mixed", n_v=96, n_u=64)
+    t = upload(p)
+    plan = plan_for(p)
+    plan.sort(t["uvw"])
+    v = wl.complex_noise(25, p.n_vis, 1.0)
+    g = plan.adjoint(torch.from_numpy(v).to(device()), t["g_uv"], t["g_w"], t["uvw"])
+    ref, _ = oracle.grid(v, p.g_uv, p.g_w, p.uvw, p.offsets, plan.shape)
+    assert rel_l2(g.cpu().numpy(), ref) <= REL_L2_FP32

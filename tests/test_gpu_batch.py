@@ -1,0 +1,124 @@
+"""Batched degridding (row a7): several independent problems in one
+persistent launch replayed from a HIP graph; and the tile-size tuner."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2102_12739_amd import workload as wl
+from paper_2102_12739_amd.degrid import Batch, DegridError, Plan
+from tests.gpu_common import REL_L2_FP32, announce, device, plan_for, rel_l2, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(seed=41):
+    return wl.batched(seed=seed, n_problems=8, s_range=(1, 6), exp_range=(4, 11), n_v=64, n_u=96)
+
+
+def test_batch_equals_separate_runs_and_oracle_over_replays():
+    probs = _small_batch()
+    announce("batch small: " + ", ".join(f"S={p.n_subgrids} os={p.os_uv} N={p.n_vis}" for p in probs))
+    ts = [upload(p) for p in probs]
+    plans = [plan_for(p, n_b=n_b) for p, n_b in zip(probs, [64, 32, 1, 7, 64, 16, 8, 64])]
+    singles = [pl.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy() for pl, t in zip(plans, ts)]
+    refs = [oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)[0] for p in probs]
+    batch = Batch(plans)
+    args = [(t["sub"], t["g_uv"], t["g_w"], t["uvw"]) for t in ts]
+    outs = [torch.full((p.n_vis,), float("nan"), dtype=torch.complex64, device=device()) for p in probs]
+    for replay in range(4):
+        for o in outs:
+            o.fill_(float("nan"))          # eager work between replays
+        batch.execute(args, outs=outs)
+        torch.cuda.synchronize()
+        for i, (o, single, ref) in enumerate(zip(outs, singles, refs)):
+            got = o.cpu().numpy()
+            assert np.array_equal(got, single), (replay, i)
+            assert rel_l2(got, ref) <= REL_L2_FP32
+    assert batch.oob_count() == 0
+
+
+def test_batch_pointer_change_reuploads_arguments():
+    probs = _small_batch(seed=42)
+    ts = [upload(p) for p in probs]
+    plans = [plan_for(p) for p in probs]
+    batch = Batch(plans)
+    args = [(t["sub"], t["g_uv"], t["g_w"], t["uvw"]) for t in ts]
+    first = [o.cpu().numpy() for o in batch.execute(args)]
+    # new subgrid contents in new buffers, new outputs
+    args2 = [(t["sub"] * 2, t["g_uv"], t["g_w"], t["uvw"]) for t in ts]
+    second = [o.cpu().numpy() for o in batch.execute(args2)]
+    torch.cuda.synchronize()
+    for a, b in zip(first, second):
+        np.testing.assert_allclose(b, 2 * a, rtol=1e-6, atol=1e-6)
+
+
+def test_batch_counts_out_of_range_over_all_problems():
+    probs = _small_batch(seed=43)
+    probs[2].uvw[0] = (np.nan, 5.0, 1.5)
+    probs[5].uvw[-1] = (1e9, 5.0, 1.5)
+    ts = [upload(p) for p in probs]
+    batch = Batch([plan_for(p) for p in probs])
+    batch.execute([(t["sub"], t["g_uv"], t["g_w"], t["uvw"]) for t in ts])
+    assert batch.oob_count() == 2
+
+
+def test_batch_rejects_mixed_storage_dtypes():
+    probs = _small_batch(seed=44)[:2]
+    plans = [plan_for(probs[0]), plan_for(probs[1], grid_dtype="cbf16")]
+    with pytest.raises(DegridError):
+        Batch(plans)
+
+
+def test_batched_workload_full_size():
+    """Eight problems with S in 4..64, counts log-uniform in [2^8, 2^18] and
+    os in {8, 16, 32}, all in one launch; every output against the oracle."""
+    probs = wl.batched(seed=2)
+    announce("batch full: " + ", ".join(f"S={p.n_subgrids} os={p.os_uv} N={p.n_vis}" for p in probs))
+    ts = [upload(p) for p in probs]
+    plans = [plan_for(p) for p in probs]
+    batch = Batch(plans)
+    outs = batch.execute([(t["sub"], t["g_uv"], t["g_w"], t["uvw"]) for t in ts])
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+        assert rel_l2(o.cpu().numpy(), ref) <= REL_L2_FP32
+    del ts
+
+
+def test_tuner_keeps_results_and_caches_choice(tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("DG_TUNE_CACHE", str(cache))
+    p = wl.make_problem("tune", [20000, 3000, 100], seed=45, kind="mixed")
+    t = upload(p)
+    plan = plan_for(p)
+    before = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    info = plan.tune(t["sub"], t["g_uv"], t["g_w"], t["uvw"])
+    assert info["n_b"] in (8, 16, 32, 64)
+    after = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    assert np.array_equal(before, after)
+    assert cache.exists() and cache.read_text().strip()
+    again = plan_for(p)            # n_b = 0: the cached choice is used
+    assert again.info()["n_b"] == info["n_b"]
+
+
+def test_batch_of_sorted_plans_and_stale_batch_is_refused():
+    probs = _small_batch(seed=46)
+    ts = [upload(p) for p in probs]
+    plans = [plan_for(p) for p in probs]
+    stale = Batch(plans)
+    for pl, t in zip(plans, ts):
+        pl.sort(t["uvw"])
+    args = [(t["sub"], t["g_uv"], t["g_w"], t["uvw"]) for t in ts]
+    with pytest.raises(DegridError) as e:
+        stale.execute(args)
+    assert e.value.status == 5
+    batch = Batch(plans)
+    outs = batch.execute(args)
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+        assert rel_l2(o.cpu().numpy(), ref) <= REL_L2_FP32

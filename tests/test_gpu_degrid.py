@@ -194,3 +194,72 @@ def test_injected_allocation_failure(monkeypatch):
     with pytest.raises(DegridError) as e:
         plan_for(p)
     assert e.value.status == 3
+
+
+def test_sorted_work_order_gives_identical_outputs_at_full_size():
+    """degrid_plan_sort reorders the work (Z-order of cells); every visibility
+    keeps its own sum, so outputs are bitwise those of the input order."""
+    p = wl.paper_scale(seed=1)
+    announce("sorted work order, paper scale")
+    t = upload(p)
+    plan = plan_for(p)
+    plain = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    plan.sort(t["uvw"])
+    assert plan.info()["sorted"] == 1
+    got = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    assert np.array_equal(got, plain)
+    ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert rel_l2(got, ref) <= REL_L2_FP32
+    plan.sort(None)
+    assert plan.info()["sorted"] == 0
+    again = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    assert np.array_equal(again, plain)
+
+
+def test_sorted_work_order_with_out_of_range_and_empty_subgrids():
+    p = wl.make_problem("sorted-oob", [0, 900, 0, 1, 700, 0], seed=24, kind="mixed", n_v=40, n_u=48)
+    p.uvw[3] = (np.nan, 20.0, 1.5)
+    p.uvw[10] = (-5.0, 20.0, 1.5)
+    p.uvw[905] = (70000.0, 20.0, 1.5)
+    t = upload(p)
+    plan = plan_for(p, n_b=16)
+    plan.sort(t["uvw"])
+    got = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    ref, oob = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert plan.oob_count() == oob == 3
+    assert rel_l2(got, ref) <= REL_L2_FP32
+    assert got[3] == 0 and got[10] == 0 and got[905] == 0
+
+
+@pytest.mark.parametrize("grid_dtype,gcf_dtype", [("c64", "f32"), ("cbf16", "f16"), ("cf16", "f32")])
+def test_every_kernel_variant_gives_the_same_outputs(grid_dtype, gcf_dtype):
+    """The variants differ only in where a tile's cells are read from (LDS copy
+    of the tile's bounding box, or the caches); each visibility's arithmetic is
+    the same, so outputs are bitwise equal, sorted or not, dense or sparse."""
+    p = wl.make_problem("variants", [6000, 40, 0, 3000, 1], seed=26, kind="mixed", n_v=80, n_u=112,
+                        os_uv=8, os_w=16)
+    p.uvw[7] = (np.nan, 1.0, 1.5)
+    t = upload(p, grid_dtype, gcf_dtype)
+    plan = plan_for(p, grid_dtype=grid_dtype, gcf_dtype=gcf_dtype)
+    n_var = plan.info()["n_kernels"]
+    assert n_var >= 2
+    outs = []
+    for sort in (False, True):
+        if sort:
+            plan.sort(t["uvw"])
+        for k in range(n_var):
+            for n_b in (64, 13):
+                plan.set_kernel(k, n_b)
+                assert plan.info()["kernel"] == k
+                outs.append(plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy())
+                assert plan.oob_count() == 1
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    from paper_2102_12739_amd import workload as w2
+    deq = w2.storage_to_complex128(w2.complex_to_storage(p.subgrids, grid_dtype), grid_dtype)
+    tdt = np.float32 if gcf_dtype == "f32" else np.float16
+    ref, _ = oracle.degrid(deq, p.g_uv.astype(tdt), p.g_w.astype(tdt), p.uvw, p.offsets)
+    assert rel_l2(outs[0], ref) <= REL_L2_FP32
+    assert outs[0][7] == 0
+    with pytest.raises(Exception):
+        plan.set_kernel(n_var, 0)
