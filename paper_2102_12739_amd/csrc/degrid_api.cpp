@@ -94,11 +94,27 @@ dg_status validate_offsets(int64_t n_sub, const int64_t* off) {
 
 struct DeviceScratch {
     Tile* tiles = nullptr;
+    uint32_t* tile_vis = nullptr;           // [n_tiles][kMaxNb]
+    const uint32_t** perm_table = nullptr;  // per problem: work-order permutation or nullptr
     Ctl* ctl = nullptr;
     int64_t n_tiles = 0;
+    int32_t n_problems = 0;
 };
 
-dg_status alloc_scratch(DeviceScratch& ds, const std::vector<Tile>& tiles, hipStream_t stream) {
+void free_tiles(DeviceScratch& ds) {
+    if (ds.tiles) (void)hipFree(ds.tiles);
+    if (ds.tile_vis) (void)hipFree(ds.tile_vis);
+    if (ds.perm_table) (void)hipFree(ds.perm_table);
+    ds.tiles = nullptr;
+    ds.tile_vis = nullptr;
+    ds.perm_table = nullptr;
+    ds.n_tiles = 0;
+}
+
+// Uploads the tile list and expands it into per-item visibility indices
+// (through each problem's permutation). Allocates; synchronises 'stream'.
+dg_status alloc_scratch(DeviceScratch& ds, const std::vector<Tile>& tiles,
+                        const std::vector<const uint32_t*>& perms, hipStream_t stream) {
     if (fault_injected("alloc")) return fail(DG_ERR_NOMEM, "allocation failure injected (DG_FAULT_INJECT=alloc)");
     hipError_t e;
     if (!ds.ctl) {
@@ -107,13 +123,23 @@ dg_status alloc_scratch(DeviceScratch& ds, const std::vector<Tile>& tiles, hipSt
         e = hipMemsetAsync(ds.ctl, 0, sizeof(Ctl), stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(control block)");
     }
-    if (ds.tiles) { (void)hipFree(ds.tiles); ds.tiles = nullptr; }
+    (void)hipStreamSynchronize(stream);
+    free_tiles(ds);
     ds.n_tiles = (int64_t)tiles.size();
+    ds.n_problems = (int32_t)perms.size();
     if (!tiles.empty()) {
         e = hipMalloc(&ds.tiles, tiles.size() * sizeof(Tile));
         if (e != hipSuccess) { ds.tiles = nullptr; return hip_fail(e, "hipMalloc(tile list)"); }
+        e = hipMalloc(&ds.tile_vis, tiles.size() * kMaxNb * sizeof(uint32_t));
+        if (e != hipSuccess) { ds.tile_vis = nullptr; return hip_fail(e, "hipMalloc(tile items)"); }
+        e = hipMalloc(&ds.perm_table, perms.size() * sizeof(const uint32_t*));
+        if (e != hipSuccess) { ds.perm_table = nullptr; return hip_fail(e, "hipMalloc(permutation table)"); }
         e = hipMemcpyAsync(ds.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, stream);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tile list)");
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ds.perm_table, perms.data(), perms.size() * sizeof(const uint32_t*),
+                               hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = launch_expand_tiles(ds.tiles, ds.n_tiles, ds.perm_table, ds.tile_vis, stream);
+        if (e != hipSuccess) return hip_fail(e, "uploading the tile list");
     }
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(plan upload)");
@@ -121,7 +147,7 @@ dg_status alloc_scratch(DeviceScratch& ds, const std::vector<Tile>& tiles, hipSt
 }
 
 void free_scratch(DeviceScratch& ds) {
-    if (ds.tiles) (void)hipFree(ds.tiles);
+    free_tiles(ds);
     if (ds.ctl) (void)hipFree(ds.ctl);
     ds = DeviceScratch{};
 }
@@ -132,8 +158,10 @@ struct dg_plan_ {
     dg_desc desc{};
     int64_t n_sub = 0;
     std::vector<int64_t> offsets;
-    int32_t n_b = 0;
+    int32_t n_b_req = 0;                   // requested tile size
+    int32_t n_b = 0;                       // tile size used (at most the variant's limit)
     int32_t variant = 0;
+    std::vector<Tile> tiles;               // host copy of the tile list
     int32_t blocks = 0;                    // persistent grid of the degrid kernel
     int32_t blocks_adj = 0;                // persistent grid of the adjoint kernel
     int32_t cap[kMaxVariants] = {};        // resident workgroups per degrid variant
@@ -265,26 +293,31 @@ void tune_cache_store(const std::string& key, int32_t n_b, int32_t variant) {
 // Default tile size and kernel variant when neither the caller nor the tuning
 // cache fixes them.
 constexpr int32_t kDefaultNb = 64;
-constexpr int32_t kDefaultVariant = 2;
+constexpr int32_t kDefaultVariant = 4;
 
 // Smallest tile worth staging when tiles are cut to fit the box.
 constexpr int kMinStagedTile = 16;
+// The kernels pad LDS box rows to a width congruent to 8 modulo 16 cells.
+constexpr int kBoxRowPad = 16;
 
-dg_status rebuild_tiles(dg_plan_* p, int32_t n_b, hipStream_t stream) {
+dg_status rebuild_tiles(dg_plan_* p, int32_t n_b_req, hipStream_t stream) {
     const int box = degrid_variant_box_bytes(p->variant);
+    const int32_t n_b = std::min<int32_t>(n_b_req, degrid_variant_max_nb(p->variant));
     std::vector<Tile> tiles;
     if (box > 0 && !p->start.empty()) {
         const int64_t cap = box / (int64_t)(grid_elem_bytes(p->desc.grid_dtype) * kSupportW);
         tiles = build_tiles_fitted(p->n_sub, p->offsets.data(), p->start.data(), n_b, kSupportUV, cap,
-                                   std::min<int>(kMinStagedTile, n_b), 0);
+                                   std::min<int>(kMinStagedTile, n_b), 0, kBoxRowPad);
     } else {
         tiles = build_tiles(p->n_sub, p->offsets.data(), n_b, 0);
     }
-    dg_status s = alloc_scratch(p->ds, tiles, stream);
+    dg_status s = alloc_scratch(p->ds, tiles, {p->d_perm}, stream);
     if (s != DG_OK) return s;
+    p->n_b_req = n_b_req;
     p->n_b = n_b;
     p->version++;
     p->q = split_queues(tiles);
+    p->tiles.swap(tiles);
     p->blocks = blocks_for(p->cap[p->variant], p->ds.n_tiles);
     p->blocks_adj = blocks_for(p->cap_adj, p->ds.n_tiles);
     return DG_OK;
@@ -295,6 +328,7 @@ LaunchParams params_for(const dg_plan_* p, const Problem& pr) {
     lp.prob = pr;
     lp.probs = nullptr;
     lp.tiles = p->ds.tiles;
+    lp.tile_vis = p->ds.tile_vis;
     lp.ctl = p->ds.ctl;
     lp.q = p->q;
     return lp;
@@ -449,7 +483,7 @@ dg_status degrid_plan_sort(dg_plan p, const double* uvw, hipStream_t stream) {
             (void)hipFree(p->d_perm);
             p->d_perm = nullptr;
             p->start.clear();
-            return rebuild_tiles(p, p->n_b, stream);
+            return rebuild_tiles(p, p->n_b_req, stream);
         }
         return DG_OK;
     }
@@ -482,7 +516,7 @@ dg_status degrid_plan_sort(dg_plan p, const double* uvw, hipStream_t stream) {
         p->start.clear();
         return hip_fail(e, "computing start cells");
     }
-    return rebuild_tiles(p, p->n_b, stream);
+    return rebuild_tiles(p, p->n_b_req, stream);
 }
 
 dg_status degrid_plan_set_kernel(dg_plan p, int32_t kernel, int32_t n_b, hipStream_t stream) {
@@ -491,7 +525,7 @@ dg_status degrid_plan_set_kernel(dg_plan p, int32_t kernel, int32_t n_b, hipStre
         return fail(DG_ERR_INVALID_ARG, "kernel must be in [-1, %d), got %d", degrid_variant_count(), kernel);
     if (n_b < 0 || n_b > kMaxNb) return fail(DG_ERR_INVALID_ARG, "n_b must be in [0, %d], got %d", kMaxNb, n_b);
     if (kernel >= 0) p->variant = kernel;
-    return rebuild_tiles(p, n_b > 0 ? n_b : p->n_b, stream);
+    return rebuild_tiles(p, n_b > 0 ? n_b : p->n_b_req, stream);
 }
 
 dg_status degrid_destroy(dg_plan p) {
@@ -523,10 +557,20 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
     b->grid_dtype = plans[0]->desc.grid_dtype;
     b->gcf_dtype = plans[0]->desc.gcf_dtype;
     b->device = plans[0]->device;
+    const int max_nb = degrid_variant_max_nb(plans[0]->variant);
     std::vector<Tile> tiles;
+    std::vector<const uint32_t*> perms;
     for (int32_t i = 0; i < n; ++i) {
-        std::vector<Tile> t = build_tiles(plans[i]->n_sub, plans[i]->offsets.data(), plans[i]->n_b, (uint16_t)i);
-        tiles.insert(tiles.end(), t.begin(), t.end());
+        for (Tile t : plans[i]->tiles) {
+            if (t.count > max_nb) {
+                degrid_batch_destroy(b);
+                return fail(DG_ERR_INVALID_ARG, "plan %d has tiles of %d visibilities; plan 0's kernel takes at most %d",
+                            i, (int)t.count, max_nb);
+            }
+            t.problem = (uint16_t)i;
+            tiles.push_back(t);
+        }
+        perms.push_back(plans[i]->d_perm);
     }
     dg_status s = DG_OK;
     hipError_t e;
@@ -534,7 +578,7 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
         degrid_batch_destroy(b);
         return st;
     };
-    s = alloc_scratch(b->ds, tiles, nullptr);
+    s = alloc_scratch(b->ds, tiles, perms, nullptr);
     if (s != DG_OK) return bail(s);
     b->q = split_queues(tiles);
     b->blocks = blocks_for(plans[0]->cap[plans[0]->variant], b->ds.n_tiles);
@@ -550,6 +594,7 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
         LaunchParams lp{};
         lp.probs = b->d_probs;
         lp.tiles = b->ds.tiles;
+        lp.tile_vis = b->ds.tile_vis;
         lp.ctl = b->ds.ctl;
         lp.q = b->q;
         e = hipGraphCreate(&b->graph, 0);

@@ -205,10 +205,8 @@ __device__ __forceinline__ float load_gcf(const void* table, int64_t idx) {
 // power-of-two os; the cell is k / os, the oversample index k mod os, and the
 // first tap sits W/2 - 1 cells below the cell. Returns false when the
 // neighbourhood leaves the subgrid or the coordinate is not finite.
-__device__ __forceinline__ bool vis_coords(const Problem& pr, int64_t i, int32_t& cell,
-                                           int32_t& tab, int32_t& ow, int32_t& x_start, int32_t& y_start) {
-    const double* c = pr.uvw + 3 * i;
-    const double u = c[0], v = c[1], w = c[2];
+__device__ __forceinline__ bool coords_from(const Problem& pr, double u, double v, double w, int32_t& cell,
+                                            int32_t& tab, int32_t& ow, int32_t& x_start, int32_t& y_start) {
     const bool ok = (u >= 3.0) & (u < pr.hi_u) & (v >= 3.0) & (v < pr.hi_v) &
                     (w >= 1.0) & (w < pr.hi_w);
     if (!ok) return false;
@@ -228,6 +226,12 @@ __device__ __forceinline__ bool vis_coords(const Problem& pr, int64_t i, int32_t
     x_start = x0;
     y_start = y0;
     return true;
+}
+
+__device__ __forceinline__ bool vis_coords(const Problem& pr, int64_t i, int32_t& cell,
+                                           int32_t& tab, int32_t& ow, int32_t& x_start, int32_t& y_start) {
+    const double* c = pr.uvw + 3 * i;
+    return coords_from(pr, c[0], c[1], c[2], cell, tab, ow, x_start, y_start);
 }
 
 // Coordinates and the G_w-weighted visibility of one visibility (adjoint).
@@ -298,15 +302,56 @@ __device__ __forceinline__ int wave_max(int x) {
     return x;
 }
 
-// Scalar-cache view of a table: loads through it with a wave-uniform address
-// become scalar loads (the tables are read-only for the whole launch).
+// Scalar-cache view of read-only data: loads through it with a wave-uniform
+// address become scalar loads.
 typedef const __attribute__((address_space(4))) float* ConstF32Ptr;
 typedef const __attribute__((address_space(4))) uint32_t* ConstU32Ptr;
+typedef const __attribute__((address_space(4))) Tile* ConstTilePtr;
+typedef const __attribute__((address_space(4))) Problem* ConstProblemPtr;
 
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
     return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ Tile load_tile(const Tile* tiles, int t) {
+    const ConstTilePtr p = (ConstTilePtr)uniform_u64((uint64_t)tiles) + t;
+    Tile x;
+    x.begin = p->begin;
+    x.sub = p->sub;
+    x.count = p->count;
+    x.problem = p->problem;
+    return x;
+}
+
+// The fields of a batch problem the degrid kernel uses, read through the
+// scalar cache.
+__device__ __forceinline__ Problem load_problem(const Problem* probs, int i) {
+    const ConstProblemPtr p = (ConstProblemPtr)uniform_u64((uint64_t)probs) + i;
+    Problem x{};
+    x.subgrids = p->subgrids;
+    x.g_uv = p->g_uv;
+    x.g_w = p->g_w;
+    x.uvw = p->uvw;
+    x.vis = p->vis;
+    x.n_v = p->n_v;
+    x.n_u = p->n_u;
+    x.n_w = p->n_w;
+    x.log2_os_uv = p->log2_os_uv;
+    x.log2_os_w = p->log2_os_w;
+    x.guv_bytes = p->guv_bytes;
+    x.sub_bytes = p->sub_bytes;
+    x.hi_u = p->hi_u;
+    x.hi_v = p->hi_v;
+    x.hi_w = p->hi_w;
+    return x;
+}
+
+__device__ __forceinline__ const double* problem_uvw(const LaunchParams& P, int problem) {
+    if (!P.probs) return P.prob.uvw;
+    const ConstProblemPtr p = (ConstProblemPtr)uniform_u64((uint64_t)P.probs) + problem;
+    return p->uvw;
 }
 
 // G_w[o_w][0..3] as four floats, read through the scalar cache.
@@ -323,107 +368,169 @@ __device__ __forceinline__ float4 load_gw_row(uint64_t g_w, int ow) {
     }
 }
 
+
+// Waits for this wavefront's outstanding vector-memory operations, including
+// loads that write LDS directly.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // LDS box of one wavefront: a copy of the cells of a tile's bounding box,
-// row-major, split into two planes of 16 bytes per cell (w 0-1 and w 2-3 of
-// complex64; the whole cell for 16-bit storage) so that eight lanes reading
-// neighbouring cells touch one contiguous 128-byte span of banks.
-template <int G, int BOX>
-__device__ __forceinline__ void lds_w4(const char* box, uint32_t off, uint32_t (&raw)[GridTraits<G>::kWords]) {
+// row-major. Complex64 cells are split into two planes of 16 bytes (w 0-1
+// and w 2-3), plane 1 starting plane1 bytes after plane 0, so that eight
+// lanes reading neighbouring cells touch one contiguous 128-byte span.
+template <int G>
+__device__ __forceinline__ void lds_w4(const char* box, uint32_t off, uint32_t plane1,
+                                       uint32_t (&raw)[GridTraits<G>::kWords]) {
     const uint4 a = *reinterpret_cast<const uint4*>(box + off);
     raw[0] = a.x; raw[1] = a.y; raw[2] = a.z; raw[3] = a.w;
     if constexpr (G == kGridC64) {
-        const uint4 b = *reinterpret_cast<const uint4*>(box + BOX / 2 + off);
+        const uint4 b = *reinterpret_cast<const uint4*>(box + plane1 + off);
         raw[4] = b.x; raw[5] = b.y; raw[6] = b.z; raw[7] = b.w;
     }
 }
 
-// Weighted sums of one tile's visibilities, eight at a time. Lane j holds the
-// coordinate-stage results of visibility j: a_off (byte offset of its first
-// tap in the LDS box, or in the subgrid; kOutOfRange in the subgrid when out
-// of range), g_off (byte offset of its G_uv block, kOutOfRange when out of
-// range) and ow (its G_w row); v_readlane hands them to the whole wavefront.
-// STAGED selects the LDS box or the subgrid in HBM (through the caches).
-template <int G, int F, int BOX, bool STAGED>
-__device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, int g_off, int ow,
-                                            __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rg,
-                                            uint64_t g_w, uint32_t lane_a, uint32_t lane_g,
-                                            const char* box) {
-    using GT = GridTraits<G>;
+// Subgrid values of eight visibilities, fetched ahead of their arithmetic so
+// that the loads of one group overlap the sums of the previous one.
+template <int G>
+struct Fetch8 {
+    uint32_t raw[8][GridTraits<G>::kWords];
+};
+
+// Lane j holds the coordinate-stage results of visibility j: a_off (byte
+// offset of its first tap in the LDS box or in the subgrid) and ow (its G_w
+// row); v_readlane hands them to the whole wavefront.
+template <int G, bool STAGED>
+__device__ __forceinline__ void fetch8(Fetch8<G>& f, int g0, int a_off, __amdgpu_buffer_rsrc_t ra,
+                                       uint32_t lane_a, const char* box, uint32_t plane1) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t aj = (uint32_t)__builtin_amdgcn_readlane(a_off, g0 + k);
+        if constexpr (STAGED) {
+            lds_w4<G>(box, lane_a + aj, plane1, f.raw[k]);
+        } else {
+            load_w4<G>(ra, lane_a + aj, f.raw[k]);
+        }
+    }
+}
+
+// Weighted sums of visibilities g0 .. g0+7 from their fetched values; gv[k]
+// is this lane's G_uv weight of visibility g0 + k, and the G_w rows come
+// through the scalar cache. Results land in out[g0 .. g0+7].
+template <int G, int F>
+__device__ __forceinline__ void sum8(const Fetch8<G>& f, const float* gv, int ow, uint64_t g_w, float2* out,
+                                     int g0) {
     const int lane = lane_id();
-    for (int g0 = 0; g0 < count; g0 += 8) {
-        uint32_t raw[8][GT::kWords];
-        float guv[8];
-        float4 gw[8];
+    float pre[8], pim[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int j = g0 + k;   // lanes >= count hold out-of-range records
-            const uint32_t aj = (uint32_t)__builtin_amdgcn_readlane(a_off, j);
-            const uint32_t gj = (uint32_t)__builtin_amdgcn_readlane(g_off, j);
-            gw[k] = load_gw_row<F>(g_w, __builtin_amdgcn_readlane(ow, j));
-            guv[k] = load_gcf_rsrc<F>(rg, gj + lane_g);
-            if constexpr (STAGED) {
-                lds_w4<G, BOX>(box, lane_a + aj, raw[k]);
-            } else {
-                load_w4<G>(ra, lane_a + aj, raw[k]);
-            }
-        }
-        float pre[8], pim[8];
+    for (int k = 0; k < 8; ++k) {
+        const float4 gw = load_gw_row<F>(g_w, __builtin_amdgcn_readlane(ow, g0 + k));
+        float re[4], im[4];
+        widen_w4<G>(f.raw[k], re, im);
+        const float sr = gw.x * re[0] + gw.y * re[1] + gw.z * re[2] + gw.w * re[3];
+        const float si = gw.x * im[0] + gw.y * im[1] + gw.z * im[2] + gw.w * im[3];
+        pre[k] = gv[k] * sr;
+        pim[k] = gv[k] * si;
+    }
+    reduce8(pre);
+    reduce8(pim);
+    if ((lane & 7) == 0) out[g0 + (lane >> 3)] = make_float2(pre[0], pim[0]);
+}
+
+// All visibilities of a tile, groups of eight in a two-stage pipeline.
+template <int G, int F, int NB, bool STAGED>
+__device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, int ow, const float* gv,
+                                            __amdgpu_buffer_rsrc_t ra, uint64_t g_w, uint32_t lane_a,
+                                            const char* box, uint32_t plane1) {
+    Fetch8<G> buf[2];
+    fetch8<G, STAGED>(buf[0], 0, a_off, ra, lane_a, box, plane1);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            float re[4], im[4];
-            widen_w4<G>(raw[k], re, im);
-            const float sr = gw[k].x * re[0] + gw[k].y * re[1] + gw[k].z * re[2] + gw[k].w * re[3];
-            const float si = gw[k].x * im[0] + gw[k].y * im[1] + gw[k].z * im[2] + gw[k].w * im[3];
-            pre[k] = guv[k] * sr;
-            pim[k] = guv[k] * si;
+    for (int g0 = 0; g0 < NB; g0 += 8) {
+        if (g0 < count) {
+            if (g0 + 8 < NB && g0 + 8 < count)
+                fetch8<G, STAGED>(buf[((g0 / 8) + 1) & 1], g0 + 8, a_off, ra, lane_a, box, plane1);
+            sum8<G, F>(buf[(g0 / 8) & 1], gv + g0, ow, g_w, out, g0);
         }
-        reduce8(pre);
-        reduce8(pim);
-        if ((lane & 7) == 0) out[g0 + (lane >> 3)] = make_float2(pre[0], pim[0]);
     }
 }
 
 // BOX: bytes of LDS per wavefront for the staged copy of a tile's cells
-// (0: always gather through the caches).
-template <int G, int F, int BOX>
-__global__ __launch_bounds__(kBlockThreads) void degrid_kernel(LaunchParams P) {
+// (0: always gather through the caches). NB: largest tile; the tile's G_uv
+// weights are held in NB registers per lane.
+//
+// Each wavefront works on one tile while the next one is on its way: the
+// next tile's header and visibility indices are requested when the current
+// tile starts, its coordinates while the current tile is gathered, and the
+// tile after it is popped from the queue one tile ahead.
+template <int G, int F, int BOX, int NB>
+__global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P) {
     using GT = GridTraits<G>;
-    constexpr int kBoxChunks = BOX > 0 ? BOX / 16 : 1;
-    __shared__ float2 s_out[kWavesPerBlock][kMaxNb];
-    __shared__ uint4 s_box[kWavesPerBlock][kBoxChunks];
+    static_assert(NB % 8 == 0 && NB <= kMaxNb, "tile size");
+    constexpr int kBoxBytes = BOX > 0 ? BOX : 16;
+    __shared__ float2 s_out[kWavesPerBlock][NB];
+    __shared__ __attribute__((aligned(16))) char s_box[kWavesPerBlock][kBoxBytes];
 
     const int lane = lane_id();
     const int wv = (int)(threadIdx.x / kWave);
     QueueState st{xcc_id() % P.q.n_queues, 0};
     uint32_t wave_oob = 0;
 
+    // current tile and its coordinates (in flight until the loop needs them)
     int t = pop_tile(P.q, P.ctl, st);
-    while (t >= 0) {
-        const Tile tile = uniform_copy(P.tiles[t]);
-        const int t_next = pop_tile(P.q, P.ctl, st);
-        const Problem pr = P.probs ? uniform_copy(P.probs[tile.problem]) : P.prob;
-        const int count = tile.count;
-
-        // Coordinate stage: lane j handles the j-th visibility of the tile.
-        int64_t my_vis = 0;
-        bool in_range = false;
-        int x0 = 0, y0 = 0, cell = 0, tab = 0, ow = 0;
-        if (lane < count) {
-            my_vis = pr.perm ? (int64_t)pr.perm[tile.begin + lane] : tile.begin + lane;
-            in_range = vis_coords(pr, my_vis, cell, tab, ow, x0, y0);
-            if (!in_range) ow = 0;
+    Tile tc{};
+    int64_t vis_c = 0;
+    double u = 0.0, v = 0.0, w = 0.0;
+    if (t >= 0) {
+        tc = load_tile(P.tiles, t);
+        vis_c = P.tile_vis[(int64_t)t * kMaxNb + lane];
+        const double* uvw = problem_uvw(P, tc.problem);
+        if (lane < tc.count) {
+            u = uvw[3 * vis_c];
+            v = uvw[3 * vis_c + 1];
+            w = uvw[3 * vis_c + 2];
         }
-        wave_oob += (uint32_t)__popcll(__ballot(lane < count && !in_range));
-        const int g_off = in_range ? tab * (int)GcfTraits<F>::kBytes : (int)kOutOfRange;
+    }
+    int t_nxt = t >= 0 ? pop_tile(P.q, P.ctl, st) : -1;
 
-        const char* sub_base = static_cast<const char*>(pr.subgrids) + (int64_t)tile.sub * pr.sub_bytes;
+    while (t >= 0) {
+        const Problem pr = P.probs ? load_problem(P.probs, tc.problem) : P.prob;
+        const int count = tc.count;
+
+        // Coordinate stage of the current tile: lane j, visibility j.
+        int32_t x0 = 0, y0 = 0, cell = 0, tab = 0, ow = 0;
+        bool in_range = false;
+        if (lane < count) in_range = coords_from(pr, u, v, w, cell, tab, ow, x0, y0);
+        if (!in_range) ow = 0;
+        wave_oob += (uint32_t)__popcll(__ballot(lane < count && !in_range));
+
+        // Next tile: header and visibility indices.
+        const bool has_next = t_nxt >= 0;
+        Tile tn{};
+        int64_t vis_n = 0;
+        if (has_next) {
+            tn = load_tile(P.tiles, t_nxt);
+            vis_n = P.tile_vis[(int64_t)t_nxt * kMaxNb + lane];
+        }
+        const int t_after = has_next ? pop_tile(P.q, P.ctl, st) : -1;
+
+        const char* sub_base = static_cast<const char*>(pr.subgrids) + (int64_t)tc.sub * pr.sub_bytes;
         const __amdgpu_buffer_rsrc_t ra = make_rsrc(sub_base, pr.sub_bytes);
         const __amdgpu_buffer_rsrc_t rg = make_rsrc(pr.g_uv, pr.guv_bytes);
         const uint64_t g_w = uniform_u64((uint64_t)pr.g_w);
         const uint32_t lane_g = (uint32_t)lane * GcfTraits<F>::kBytes;
 
+        // G_uv weights of the whole tile (zero for out-of-range visibilities).
+        const int g_off = in_range ? tab * (int)GcfTraits<F>::kBytes : (int)kOutOfRange;
+        float gv[NB];
+#pragma unroll
+        for (int g0 = 0; g0 < NB; g0 += 8) {
+            if (g0 < count) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    gv[g0 + k] = load_gcf_rsrc<F>(rg, (uint32_t)__builtin_amdgcn_readlane(g_off, g0 + k) + lane_g);
+            }
+        }
+
         bool staged = false;
-        int bx0 = 0, by0 = 0, bw = 0, bh = 0;
+        int bx0 = 0, by0 = 0, bw = 0, bh = 0, bp = 0;
         if constexpr (BOX > 0) {
             // bounding box of the tile's neighbourhoods
             bx0 = uniform(wave_min(in_range ? x0 : 0x7FFFFFFF));
@@ -433,55 +540,79 @@ __global__ __launch_bounds__(kBlockThreads) void degrid_kernel(LaunchParams P) {
             if (bx1 >= 0) {
                 bw = bx1 - bx0 + kSupportUV;
                 bh = by1 - by0 + kSupportUV;
-                staged = (uint32_t)(bw * bh) * kCellBytes<G> <= (uint32_t)BOX;
+                // row pitch of the LDS copy, in 16-byte chunks: congruent to 8
+                // mod 16, so two neighbouring rows read in the same LDS cycle
+                // fall on opposite halves of the banks
+                bp = bw + ((8 - bw) & 15);
+                staged = (uint32_t)(bp * bh) * kCellBytes<G> <= (uint32_t)BOX;
             }
         }
+
+        char* box = s_box[wv];
         if (staged) {
-            // Copy the box row by row: rc 16-byte chunks per row, one chunk
-            // per lane and step, four steps in flight.
+            // Copy the box with loads that write LDS directly (lane l of a step
+            // fills 16 bytes at 16 * l), all in flight at once. LDS chunk c is
+            // half c / n_slots of slot c mod n_slots (complex64), or slot c;
+            // slot (row, col) with col >= bw is row padding (filled with zeros).
             constexpr int kHalves = (int)(kCellBytes<G> / 16);   // 2 for complex64, else 1
-            const int rc = bw * kHalves;
-            const int total = rc * bh;
-            const float inv_rc = 1.0f / (float)rc;
+            const int n_slots = bp * bh;
+            const int total = n_slots * kHalves;
+            const float inv_bp = 1.0f / (float)bp;
             const uint32_t row_stride = (uint32_t)pr.n_u * pr.n_w * GT::kElemBytes;
             const uint32_t box_origin = ((uint32_t)by0 * pr.n_u + bx0) * pr.n_w * GT::kElemBytes;
-            char* box = reinterpret_cast<char*>(s_box[wv]);
-            for (int c0 = 0; c0 < total; c0 += 4 * kWave) {
-                uint4 v[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = c0 + k * kWave + lane;
-                    const int row = (int)(((float)c + 0.5f) * inv_rc);
-                    const int col = c - row * rc;
-                    const uint32_t off = c < total ? box_origin + (uint32_t)row * row_stride + (uint32_t)col * 16u
-                                                   : kOutOfRange;
-                    v[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(ra, off, 0, 0));
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = c0 + k * kWave + lane;
-                    // chunk c is half (c mod 2) of cell c / 2 for complex64
-                    const uint32_t dst = kHalves == 2 ? (uint32_t)(c & 1) * (BOX / 2) + (uint32_t)(c >> 1) * 16u
-                                                      : (uint32_t)c * 16u;
-                    if (c < total) *reinterpret_cast<uint4*>(box + dst) = v[k];
-                }
+            for (int c0 = 0; c0 < total; c0 += kWave) {
+                const int c = c0 + lane;
+                const int half = (kHalves == 2 && c >= n_slots) ? 1 : 0;
+                const int cc = c - half * n_slots;
+                const int row = (int)(((float)cc + 0.5f) * inv_bp);
+                const int col = cc - row * bp;
+                const uint32_t off = (c < total && col < bw)
+                                         ? box_origin + (uint32_t)row * row_stride + (uint32_t)col * kCellBytes<G> +
+                                               (uint32_t)half * 16u
+                                         : kOutOfRange;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    ra, (__attribute__((address_space(3))) void*)(box + c0 * 16), 16, off, 0, 0, 0);
             }
+            wait_vmem();
             wave_lds_sync();
-            // out-of-range visibilities read cell (0, 0) of the box; their
-            // weight is zero and their output is overwritten with zero
-            const int a_off = in_range ? ((y0 - by0) * bw + (x0 - bx0)) * 16 : 0;
-            const uint32_t lane_box = ((uint32_t)(lane >> 3) * bw + (lane & 7)) * 16u;
-            gather_tile<G, F, BOX, true>(s_out[wv], count, a_off, g_off, ow, ra, rg, g_w, lane_box, lane_g, box);
-        } else {
-            const int a_off = in_range ? cell * (int)GT::kElemBytes : (int)kOutOfRange;
-            const uint32_t lane_a = (uint32_t)(((lane >> 3) * pr.n_u + (lane & 7)) * pr.n_w) * GT::kElemBytes;
-            gather_tile<G, F, BOX, false>(s_out[wv], count, a_off, g_off, ow, ra, rg, g_w, lane_a, lane_g, nullptr);
+        }
+
+        // Next tile's coordinates: requested now when the gather below reads
+        // only LDS, registers and the scalar cache; after it otherwise.
+        double un = 0.0, vn = 0.0, wn = 0.0;
+        const double* uvw_n = has_next ? problem_uvw(P, tn.problem) : nullptr;
+        if (staged && has_next && lane < tn.count) {
+            un = uvw_n[3 * vis_n];
+            vn = uvw_n[3 * vis_n + 1];
+            wn = uvw_n[3 * vis_n + 2];
+        }
+
+        const uint32_t plane1 = (uint32_t)(bp * bh) * 16u;
+        const int a_off = staged ? (in_range ? ((y0 - by0) * bp + (x0 - bx0)) * 16 : 0)
+                                 : (in_range ? cell * (int)GT::kElemBytes : (int)kOutOfRange);
+        const uint32_t lane_a = staged ? ((uint32_t)(lane >> 3) * bp + (lane & 7)) * 16u
+                                       : (uint32_t)(((lane >> 3) * pr.n_u + (lane & 7)) * pr.n_w) * GT::kElemBytes;
+        if (staged)
+            gather_tile<G, F, NB, true>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box, plane1);
+        else
+            gather_tile<G, F, NB, false>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box, plane1);
+        if (!staged && has_next && lane < tn.count) {
+            un = uvw_n[3 * vis_n];
+            vn = uvw_n[3 * vis_n + 1];
+            wn = uvw_n[3 * vis_n + 2];
         }
         wave_lds_sync();
         if (lane < count)
-            static_cast<float2*>(pr.vis)[my_vis] = in_range ? s_out[wv][lane] : make_float2(0.f, 0.f);
+            static_cast<float2*>(pr.vis)[vis_c] = in_range ? s_out[wv][lane] : make_float2(0.f, 0.f);
         wave_lds_sync();
-        t = t_next;
+
+        t = t_nxt;
+        t_nxt = t_after;
+        tc = tn;
+        vis_c = vis_n;
+        u = un;
+        v = vn;
+        w = wn;
     }
     finish_launch(P.ctl, wave_oob);
 }
@@ -501,7 +632,7 @@ __global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParam
 
     int t = pop_tile(P.q, P.ctl, st);
     while (t >= 0) {
-        const Tile tile = uniform_copy(P.tiles[t]);
+        const Tile tile = load_tile(P.tiles, t);
         const int t_next = pop_tile(P.q, P.ctl, st);
         const Problem pr = P.probs ? uniform_copy(P.probs[tile.problem]) : P.prob;
         const int count = tile.count;
@@ -515,7 +646,7 @@ __global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParam
             for (int k = 0; k < 8; ++k) r.c[k] = 0.0f;
             bool in_range = false;
             if (lane < count) {
-                const int64_t i = pr.perm ? (int64_t)pr.perm[tile.begin + lane] : tile.begin + lane;
+                const int64_t i = P.tile_vis[(int64_t)t * kMaxNb + lane];
                 int32_t ow = 0, x0 = 0, y0 = 0;
                 in_range = vis_coords(pr, i, r.cell, r.tab, ow, x0, y0);
                 if (in_range) {
@@ -579,36 +710,51 @@ __global__ void start_cells_kernel(Problem pr, int64_t n, uint32_t* start) {
     start[p] = vis_coords(pr, i, cell, tab, ow, x0, y0) ? ((uint32_t)y0 << 16) | (uint32_t)x0 : kNoStart;
 }
 
+__global__ void expand_tiles_kernel(const Tile* tiles, int64_t n_tiles, const uint32_t* const* perms,
+                                    uint32_t* tile_vis) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_tiles * kMaxNb) return;
+    const Tile tl = tiles[k / kMaxNb];
+    const int j = (int)(k % kMaxNb);
+    const int64_t pos = tl.begin + (j < tl.count ? j : 0);
+    const uint32_t* perm = perms ? perms[tl.problem] : nullptr;
+    tile_vis[k] = perm ? perm[pos] : (uint32_t)pos;
+}
+
 __global__ void zero_kernel(float4* p, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
         p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// Kernel variants: the LDS box per wavefront (bytes); 0 gathers through the
-// caches only.
-constexpr int kBoxVariants[] = {0, 8192, 16384, 24576, 32768};
-constexpr int kNumVariants = sizeof(kBoxVariants) / sizeof(kBoxVariants[0]);
+// Kernel variants: (LDS box per wavefront in bytes, largest tile). Box 0
+// gathers through the caches only.
+struct Variant { int box; int nb; };
+constexpr Variant kVariants[] = {{0, 64}, {8192, 32}, {12288, 32}, {16384, 32}, {16384, 64}, {24576, 64}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <int G, int F, int BOX>
+template <int G, int F, int V>
 hipError_t launch_degrid_t(const LaunchParams& p, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((degrid_kernel<G, F, BOX>), dim3(blocks), dim3(kBlockThreads), 0, s, p);
+    hipLaunchKernelGGL((degrid_kernel<G, F, kVariants[V].box, kVariants[V].nb>), dim3(blocks), dim3(kBlockThreads),
+                       0, s, p);
     return hipGetLastError();
 }
 
-template <int G, int F, int BOX>
+template <int G, int F, int V>
 hipError_t occ_degrid_t(int* n) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, degrid_kernel<G, F, BOX>, kBlockThreads, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, degrid_kernel<G, F, kVariants[V].box, kVariants[V].nb>,
+                                                        kBlockThreads, 0);
 }
 
 template <int G, int F>
 hipError_t launch_degrid_v(const LaunchParams& p, int variant, int blocks, hipStream_t s) {
     switch (variant) {
-        case 0: return launch_degrid_t<G, F, kBoxVariants[0]>(p, blocks, s);
-        case 1: return launch_degrid_t<G, F, kBoxVariants[1]>(p, blocks, s);
-        case 2: return launch_degrid_t<G, F, kBoxVariants[2]>(p, blocks, s);
-        case 3: return launch_degrid_t<G, F, kBoxVariants[3]>(p, blocks, s);
-        case 4: return launch_degrid_t<G, F, kBoxVariants[4]>(p, blocks, s);
+        case 0: return launch_degrid_t<G, F, 0>(p, blocks, s);
+        case 1: return launch_degrid_t<G, F, 1>(p, blocks, s);
+        case 2: return launch_degrid_t<G, F, 2>(p, blocks, s);
+        case 3: return launch_degrid_t<G, F, 3>(p, blocks, s);
+        case 4: return launch_degrid_t<G, F, 4>(p, blocks, s);
+        case 5: return launch_degrid_t<G, F, 5>(p, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -616,11 +762,12 @@ hipError_t launch_degrid_v(const LaunchParams& p, int variant, int blocks, hipSt
 template <int G, int F>
 hipError_t occ_degrid_v(int variant, int* n) {
     switch (variant) {
-        case 0: return occ_degrid_t<G, F, kBoxVariants[0]>(n);
-        case 1: return occ_degrid_t<G, F, kBoxVariants[1]>(n);
-        case 2: return occ_degrid_t<G, F, kBoxVariants[2]>(n);
-        case 3: return occ_degrid_t<G, F, kBoxVariants[3]>(n);
-        case 4: return occ_degrid_t<G, F, kBoxVariants[4]>(n);
+        case 0: return occ_degrid_t<G, F, 0>(n);
+        case 1: return occ_degrid_t<G, F, 1>(n);
+        case 2: return occ_degrid_t<G, F, 2>(n);
+        case 3: return occ_degrid_t<G, F, 3>(n);
+        case 4: return occ_degrid_t<G, F, 4>(n);
+        case 5: return occ_degrid_t<G, F, 5>(n);
         default: return hipErrorInvalidValue;
     }
 }
@@ -630,7 +777,10 @@ hipError_t occ_degrid_v(int variant, int* n) {
 int degrid_variant_count() { return kNumVariants; }
 int adjoint_variant_count() { return 1; }
 int degrid_variant_box_bytes(int variant) {
-    return (variant >= 0 && variant < kNumVariants) ? kBoxVariants[variant] : -1;
+    return (variant >= 0 && variant < kNumVariants) ? kVariants[variant].box : -1;
+}
+int degrid_variant_max_nb(int variant) {
+    return (variant >= 0 && variant < kNumVariants) ? kVariants[variant].nb : -1;
 }
 
 hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int variant,
@@ -681,6 +831,15 @@ hipError_t launch_start_cells(const Problem& pr, int64_t n, uint32_t* start, hip
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(start_cells_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, pr, n, start);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_tiles(const Tile* tiles, int64_t n_tiles, const uint32_t* const* perms,
+                               uint32_t* tile_vis, hipStream_t stream) {
+    if (n_tiles <= 0) return hipSuccess;
+    const int64_t n = n_tiles * kMaxNb;
+    hipLaunchKernelGGL(expand_tiles_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, tiles, n_tiles,
+                       perms, tile_vis);
     return hipGetLastError();
 }
 

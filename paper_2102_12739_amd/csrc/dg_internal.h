@@ -54,6 +54,7 @@ struct LaunchParams {
     Problem prob;               // used when probs == nullptr
     const Problem* probs;       // per-problem table of a batch
     const Tile* tiles;
+    const uint32_t* tile_vis;   // [n_tiles][kMaxNb]: visibility index of each work item
     Ctl* ctl;
     QueueSpec q;
 };
@@ -67,6 +68,11 @@ hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int
 hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant, int blocks,
                                hipStream_t stream);
 hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t stream);
+// tile_vis[t * kMaxNb + j] = visibility index of item j of tile t: through
+// perms[tile.problem] (a work-order permutation, or nullptr for input order)
+// at position tile.begin + j; items past the tile's count repeat its first.
+hipError_t launch_expand_tiles(const Tile* tiles, int64_t n_tiles, const uint32_t* const* perms,
+                               uint32_t* tile_vis, hipStream_t stream);
 // start[p] = first tap (y0 << 16 | x0) of the visibility at work position p
 // (through pr.perm), or kNoStart when out of range.
 hipError_t launch_start_cells(const Problem& pr, int64_t n, uint32_t* start, hipStream_t stream);
@@ -82,6 +88,7 @@ hipError_t adjoint_kernel_occupancy(int gcf_kind, int variant, int* blocks_per_c
 int degrid_variant_count();
 int adjoint_variant_count();
 int degrid_variant_box_bytes(int variant);   // LDS staging bytes per wavefront (0: none)
+int degrid_variant_max_nb(int variant);      // largest tile the variant accepts
 constexpr int kMaxVariants = 8;
 
 }  // namespace dg

@@ -22,7 +22,7 @@ std::vector<Tile> build_tiles(int64_t n_sub, const int64_t* off, int nb, uint16_
 }
 
 std::vector<Tile> build_tiles_fitted(int64_t n_sub, const int64_t* off, const uint32_t* start, int nb,
-                                     int support, int64_t cap_cells, int min_fit, uint16_t problem) {
+                                     int support, int64_t cap_cells, int min_fit, uint16_t problem, int pad_to) {
     std::vector<Tile> tiles;
     for (int64_t s = 0; s < n_sub; ++s) {
         int64_t i = off[s];
@@ -37,7 +37,8 @@ std::vector<Tile> build_tiles_fitted(int64_t n_sub, const int64_t* off, const ui
                     const int32_t x = (int32_t)(st & 0xFFFFu), y = (int32_t)(st >> 16);
                     const int32_t nxl = xh < xl ? x : std::min(xl, x), nxh = xh < xl ? x : std::max(xh, x);
                     const int32_t nyl = yh < yl ? y : std::min(yl, y), nyh = yh < yl ? y : std::max(yh, y);
-                    const int64_t area = (int64_t)(nxh - nxl + support) * (nyh - nyl + support);
+                    const int64_t w = nxh - nxl + support;
+                    const int64_t area = (w + (pad_to ? ((pad_to / 2 - w) & (pad_to - 1)) : 0)) * (nyh - nyl + support);
                     if (area > cap_cells) break;
                     xl = nxl; xh = nxh; yl = nyl; yh = nyh;
                 }

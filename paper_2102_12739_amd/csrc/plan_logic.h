@@ -46,9 +46,12 @@ constexpr uint32_t kNoStart = 0xFFFFFFFFu;
 // most cap_cells cells and it has fewer than nb visibilities. If fewer than
 // min_fit visibilities fit, the tile takes nb visibilities anyway (it will
 // be gathered without staging) so that sparse regions do not become many
-// tiny tiles. Out-of-range visibilities never enlarge a box.
+// tiny tiles. Out-of-range visibilities never enlarge a box. pad_to (0 or a
+// power of two) pads the box width to the next value congruent to pad_to / 2
+// modulo pad_to, as the staging copy in LDS does.
 std::vector<Tile> build_tiles_fitted(int64_t n_sub, const int64_t* off, const uint32_t* start, int nb,
-                                     int support, int64_t cap_cells, int min_fit, uint16_t problem);
+                                     int support, int64_t cap_cells, int min_fit, uint16_t problem,
+                                     int pad_to = 0);
 
 // Split a tile list into up to kMaxQueues contiguous queues holding about
 // equal numbers of visibilities (empty queues only when there are fewer

@@ -1,7 +1,7 @@
 // Property checks of the host work decomposition, built with g++ (no HIP).
 // Prints the tiles and queues as JSON; the pytest wrapper checks properties.
 //   plan_logic_check <nb> <count>...                    fixed-size tiles
-//   plan_logic_check fitted <nb> <cap> <min_fit> <file> tiles cut to fit a box;
+//   plan_logic_check fitted <nb> <cap> <min_fit> <pad_to> <file> tiles cut to fit a box;
 //       <file>: line 1 = per-subgrid counts, line 2 = start word per visibility
 #include "plan_logic.h"
 
@@ -29,11 +29,12 @@ static void print(const std::vector<dg::Tile>& tiles) {
 int main(int argc, char** argv) {
     if (argc < 2) return 2;
     if (std::strcmp(argv[1], "fitted") == 0) {
-        if (argc != 6) return 2;
+        if (argc != 7) return 2;
         const int nb = std::atoi(argv[2]);
         const long long cap = std::atoll(argv[3]);
         const int min_fit = std::atoi(argv[4]);
-        std::ifstream f(argv[5]);
+        const int pad_to = std::atoi(argv[5]);
+        std::ifstream f(argv[6]);
         std::string l1, l2;
         std::getline(f, l1);
         std::getline(f, l2);
@@ -45,7 +46,8 @@ int main(int argc, char** argv) {
         unsigned long long w;
         while (st >> w) start.push_back((uint32_t)w);
         if ((int64_t)start.size() != off.back()) return 3;
-        print(dg::build_tiles_fitted((int64_t)off.size() - 1, off.data(), start.data(), nb, 8, cap, min_fit, 3));
+        print(dg::build_tiles_fitted((int64_t)off.size() - 1, off.data(), start.data(), nb, 8, cap, min_fit, 3,
+                                     pad_to));
         return 0;
     }
     const int nb = std::atoi(argv[1]);

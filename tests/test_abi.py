@@ -192,10 +192,10 @@ def test_queues_partition_the_tile_list_and_balance_visibilities(plan_logic, nb,
         assert max(per_q) <= share + nb and min(per_q) >= share - nb
 
 
-def _fitted(plan_logic_exe, tmp_path, nb, cap, min_fit, counts, starts):
+def _fitted(plan_logic_exe, tmp_path, nb, cap, min_fit, pad_to, counts, starts):
     f = tmp_path / "starts.txt"
     f.write_text(" ".join(map(str, counts)) + "\n" + " ".join(map(str, starts)) + "\n")
-    r = subprocess.run([plan_logic_exe, "fitted", str(nb), str(cap), str(min_fit), str(f)],
+    r = subprocess.run([plan_logic_exe, "fitted", str(nb), str(cap), str(min_fit), str(pad_to), str(f)],
                        capture_output=True, text=True, check=True)
     return json.loads(r.stdout)
 
@@ -209,8 +209,9 @@ def plan_logic_exe(tmp_path_factory):
     return str(exe)
 
 
-@pytest.mark.parametrize("seed,cap,min_fit", [(0, 512, 16), (1, 256, 8), (2, 1024, 16), (3, 64, 4)])
-def test_fitted_tiles_cover_fit_the_box_and_are_greedy(plan_logic_exe, tmp_path, seed, cap, min_fit):
+@pytest.mark.parametrize("seed,cap,min_fit,pad_to", [(0, 512, 16, 0), (1, 256, 8, 0), (2, 1024, 16, 16),
+                                                    (3, 64, 4, 0), (4, 512, 16, 16)])
+def test_fitted_tiles_cover_fit_the_box_and_are_greedy(plan_logic_exe, tmp_path, seed, cap, min_fit, pad_to):
     rng = np.random.default_rng(seed)
     nb, no_start = 64, 0xFFFFFFFF
     counts = [int(c) for c in rng.integers(0, 700, 6)] + [0, 1, 65]
@@ -222,7 +223,7 @@ def test_fitted_tiles_cover_fit_the_box_and_are_greedy(plan_logic_exe, tmp_path,
             x = int(np.clip(x + rng.integers(-3, 4), 0, 504))
             y = int(np.clip(y + rng.integers(-3, 4), 0, 504))
             starts.append(no_start if rng.random() < 0.05 else (y << 16) | x)
-    out = _fitted(plan_logic_exe, tmp_path, nb, cap, min_fit, counts, starts)
+    out = _fitted(plan_logic_exe, tmp_path, nb, cap, min_fit, pad_to, counts, starts)
     off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     covered = np.zeros(int(off[-1]), dtype=np.int64)
 
@@ -231,7 +232,10 @@ def test_fitted_tiles_cover_fit_the_box_and_are_greedy(plan_logic_exe, tmp_path,
         ys = [s >> 16 for s in starts[lo:hi] if s != no_start]
         if not xs:
             return 0
-        return (max(xs) - min(xs) + 8) * (max(ys) - min(ys) + 8)
+        w = max(xs) - min(xs) + 8
+        if pad_to:
+            w += (pad_to // 2 - w) % pad_to      # width congruent to pad_to/2 mod pad_to
+        return w * (max(ys) - min(ys) + 8)
 
     for begin, sub, count, problem in out["tiles"]:
         assert problem == 3 and 1 <= count <= nb
