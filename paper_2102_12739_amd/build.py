@@ -25,7 +25,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-ato
 def build(verbose: bool = False) -> str:
     """Compile every source and link ``libdegrid.so`` (always recompiles)."""
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, *FLAGS, "-shared", "-o", tmp, *SOURCES]
+    cmd = [HIPCC, *FLAGS, "-shared", "-Wl,--no-undefined", "-o", tmp, *SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

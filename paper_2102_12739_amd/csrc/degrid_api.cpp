@@ -165,7 +165,7 @@ struct dg_plan_ {
     int32_t blocks = 0;                    // persistent grid of the degrid kernel
     int32_t blocks_adj = 0;                // persistent grid of the adjoint kernel
     int32_t cap[kMaxVariants] = {};        // resident workgroups per degrid variant
-    int32_t cap_adj = 0;
+    int32_t cap_adj[kMaxVariants] = {};    // resident workgroups per adjoint variant
     int32_t device = 0;
     QueueSpec q{};
     DeviceScratch ds;
@@ -245,10 +245,12 @@ dg_status device_capacity(dg_plan_* p) {
         if (e != hipSuccess) return hip_fail(e, "occupancy query (degrid)");
         p->cap[v] = std::max(1, n_cu * std::max(1, occ));
     }
-    int adj = 0;
-    e = adjoint_kernel_occupancy(p->desc.gcf_dtype, 0, &adj);
-    if (e != hipSuccess) return hip_fail(e, "occupancy query (adjoint)");
-    p->cap_adj = std::max(1, n_cu * std::max(1, adj));
+    for (int v = 0; v < adjoint_variant_count(); ++v) {
+        int adj = 0;
+        e = adjoint_kernel_occupancy(p->desc.gcf_dtype, v, &adj);
+        if (e != hipSuccess) return hip_fail(e, "occupancy query (adjoint)");
+        p->cap_adj[v] = std::max(1, n_cu * std::max(1, adj));
+    }
     p->device = dev;
     return DG_OK;
 }
@@ -319,7 +321,7 @@ dg_status rebuild_tiles(dg_plan_* p, int32_t n_b_req, hipStream_t stream) {
     p->q = split_queues(tiles);
     p->tiles.swap(tiles);
     p->blocks = blocks_for(p->cap[p->variant], p->ds.n_tiles);
-    p->blocks_adj = blocks_for(p->cap_adj, p->ds.n_tiles);
+    p->blocks_adj = blocks_for(p->cap_adj[p->variant], p->ds.n_tiles);
     return DG_OK;
 }
 
@@ -394,7 +396,7 @@ dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void*
     if (p->ds.n_tiles == 0) return DG_OK;
     if (!vis || !g_uv || !g_w || !uvw) return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
     const Problem pr = problem_of(p, nullptr, g_uv, g_w, uvw, const_cast<void*>(vis), subgrids_out);
-    hipError_t e = launch_grid_adjoint(params_for(p, pr), p->desc.gcf_dtype, 0, p->blocks_adj, stream);
+    hipError_t e = launch_grid_adjoint(params_for(p, pr), p->desc.gcf_dtype, p->variant, p->blocks_adj, stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
     p->last_stream = stream;
     p->launched = true;

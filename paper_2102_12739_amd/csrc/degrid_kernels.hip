@@ -234,15 +234,6 @@ __device__ __forceinline__ bool vis_coords(const Problem& pr, int64_t i, int32_t
     return coords_from(pr, c[0], c[1], c[2], cell, tab, ow, x_start, y_start);
 }
 
-// Coordinates and the G_w-weighted visibility of one visibility (adjoint).
-struct AdjRec {
-    int32_t cell;
-    int32_t tab;
-    int32_t pad0, pad1;
-    float c[8];     // G_w[o_w][t] * V, interleaved (re, im) for t = 0..3
-};
-static_assert(sizeof(AdjRec) == 48, "AdjRec layout");
-
 // ---------------------------------------------------------------------------
 // Cross-lane reduction of eight visibilities
 // ---------------------------------------------------------------------------
@@ -618,12 +609,27 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint (gridding) kernel: scatter with float32 atomics
+// Adjoint (gridding) kernel
 // ---------------------------------------------------------------------------
+//
+// The transpose of degridding: every in-range visibility V adds
+// G_w[o_w][t_w] * G_uv[o_v][o_u][t_v][t_u] * V to the cell (y + t_v, x + t_u,
+// z + t_w). Lanes map onto the 8 x 8 (t_v, t_u) taps as in the gather. When
+// the tile's cells fit the wavefront's LDS box, contributions are summed
+// there first (LDS float atomics) and the box is added to the output once
+// with global float atomics; otherwise each contribution is a global atomic.
 
-template <int F>
+// V times the four G_w taps of one visibility, interleaved (re, im).
+struct WeightedVis {
+    float c[8];
+};
+
+template <int F, int BOX, int NB>
 __global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParams P) {
-    __shared__ AdjRec s_rec[kWavesPerBlock][kMaxNb];
+    static_assert(NB % 8 == 0 && NB <= kMaxNb, "tile size");
+    constexpr int kBoxBytes = BOX > 0 ? BOX : 16;
+    constexpr uint32_t kCell = kSupportW * 8;   // complex64 cell of 4 w values
+    __shared__ __attribute__((aligned(16))) char s_box[kWavesPerBlock][kBoxBytes];
 
     const int lane = lane_id();
     const int wv = (int)(threadIdx.x / kWave);
@@ -632,68 +638,124 @@ __global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParam
 
     int t = pop_tile(P.q, P.ctl, st);
     while (t >= 0) {
-        const Tile tile = load_tile(P.tiles, t);
+        const Tile tc = load_tile(P.tiles, t);
         const int t_next = pop_tile(P.q, P.ctl, st);
-        const Problem pr = P.probs ? uniform_copy(P.probs[tile.problem]) : P.prob;
-        const int count = tile.count;
+        const Problem pr = P.probs ? load_problem(P.probs, tc.problem) : P.prob;
+        const int count = tc.count;
 
-        {
-            AdjRec r;
-            r.cell = -1;
-            r.tab = 0;
-            r.pad0 = r.pad1 = 0;
+        // Coordinate stage; lane j also forms G_w * V of visibility j.
+        int32_t x0 = 0, y0 = 0, cell = 0, tab = 0, ow = 0;
+        bool in_range = false;
+        WeightedVis cw;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) r.c[k] = 0.0f;
-            bool in_range = false;
-            if (lane < count) {
-                const int64_t i = P.tile_vis[(int64_t)t * kMaxNb + lane];
-                int32_t ow = 0, x0 = 0, y0 = 0;
-                in_range = vis_coords(pr, i, r.cell, r.tab, ow, x0, y0);
-                if (in_range) {
-                    const float2 vv = static_cast<const float2*>(pr.vis)[i];
+        for (int q = 0; q < 8; ++q) cw.c[q] = 0.0f;
+        if (lane < count) {
+            const int64_t i = P.tile_vis[(int64_t)t * kMaxNb + lane];
+            in_range = vis_coords(pr, i, cell, tab, ow, x0, y0);
+            if (in_range) {
+                const float2 vv = static_cast<const float2*>(pr.vis)[i];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const float gw = load_gcf<F>(pr.g_w, ow * kSupportW + k);
-                        r.c[2 * k] = gw * vv.x;
-                        r.c[2 * k + 1] = gw * vv.y;
-                    }
-                } else {
-                    r.cell = -1;
-                    r.tab = 0;
+                for (int k = 0; k < 4; ++k) {
+                    const float gw = load_gcf<F>(pr.g_w, ow * kSupportW + k);
+                    cw.c[2 * k] = gw * vv.x;
+                    cw.c[2 * k + 1] = gw * vv.y;
                 }
             }
-            wave_oob += (uint32_t)__popcll(__ballot(lane < count && !in_range));
-            s_rec[wv][lane] = r;
         }
-        wave_lds_sync();
+        wave_oob += (uint32_t)__popcll(__ballot(lane < count && !in_range));
 
+        // G_uv weights of the whole tile (zero for out-of-range visibilities).
         const __amdgpu_buffer_rsrc_t rg = make_rsrc(pr.g_uv, pr.guv_bytes);
         const uint32_t lane_g = (uint32_t)lane * GcfTraits<F>::kBytes;
-        float* out = static_cast<float*>(pr.grid_out) + 2 * ((int64_t)tile.sub * pr.cells_per_sub +
-                     (int64_t)(((lane >> 3) * pr.n_u + (lane & 7)) * pr.n_w));
-
-        for (int g0 = 0; g0 < count; g0 += 8) {
-            float guv[8];
+        const int g_off = in_range ? tab * (int)GcfTraits<F>::kBytes : (int)kOutOfRange;
+        float gv[NB];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int j = g0 + k;
-                const int cell = uniform(s_rec[wv][j].cell);
-                const int tab = uniform(s_rec[wv][j].tab);
-                const bool live = (j < count) & (cell >= 0);
-                guv[k] = load_gcf_rsrc<F>(rg, live ? (uint32_t)tab * GcfTraits<F>::kBytes + lane_g : kOutOfRange);
+        for (int g0 = 0; g0 < NB; g0 += 8) {
+            if (g0 < count) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    gv[g0 + k] = load_gcf_rsrc<F>(rg, (uint32_t)__builtin_amdgcn_readlane(g_off, g0 + k) + lane_g);
             }
+        }
+
+        bool staged = false;
+        int bx0 = 0, by0 = 0, bw = 0, bh = 0, bp = 0;
+        if constexpr (BOX > 0) {
+            bx0 = uniform(wave_min(in_range ? x0 : 0x7FFFFFFF));
+            by0 = uniform(wave_min(in_range ? y0 : 0x7FFFFFFF));
+            const int bx1 = uniform(wave_max(in_range ? x0 : -1));
+            const int by1 = uniform(wave_max(in_range ? y0 : -1));
+            if (bx1 >= 0) {
+                bw = bx1 - bx0 + kSupportUV;
+                bh = by1 - by0 + kSupportUV;
+                bp = bw + ((8 - bw) & 15);
+                staged = (uint32_t)(bp * bh) * kCell <= (uint32_t)BOX;
+            }
+        }
+
+        float* out = static_cast<float*>(pr.grid_out) + 2 * (int64_t)tc.sub * pr.n_v * pr.n_u * pr.n_w;
+        const int tv = lane >> 3, tu = lane & 7;
+        if (staged) {
+            char* box = s_box[wv];
+            const int n_chunks = bp * bh * (int)(kCell / 16);
+            for (int c = lane; c < n_chunks; c += kWave)
+                *reinterpret_cast<uint4*>(box + (uint32_t)c * 16u) = make_uint4(0u, 0u, 0u, 0u);
+            wave_lds_sync();
+            const int rel = in_range ? ((y0 - by0) * bp + (x0 - bx0)) : 0;
+            const uint32_t lane_box = ((uint32_t)tv * bp + tu) * kCell;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int j = g0 + k;
-                const int cell = uniform(s_rec[wv][j].cell);
-                if (j < count && cell >= 0) {
-                    float* dst = out + 2 * (int64_t)cell;
+            for (int g0 = 0; g0 < NB; g0 += 8) {
+                if (g0 < count) {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) unsafeAtomicAdd(dst + q, guv[k] * s_rec[wv][j].c[q]);
+                    for (int k = 0; k < 8; ++k) {
+                        const int j = g0 + k;
+                        const uint32_t base = lane_box + (uint32_t)__builtin_amdgcn_readlane(rel, j) * kCell;
+                        float* dst = reinterpret_cast<float*>(box + base);
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cw.c[q]), j));
+                            atomicAdd(dst + q, gv[j] * c);
+                        }
+                    }
+                }
+            }
+            wave_lds_sync();
+            // Add the box to the output row by row: a box row is bw * 8
+            // consecutive floats both in LDS and in the subgrid, so lane l of
+            // a step adds float l and one atomic instruction covers 256
+            // contiguous bytes.
+            const int row_floats = bw * (int)(kCell / 4);
+            const float* lds_rows = reinterpret_cast<const float*>(box);
+            for (int row = 0; row < bh; ++row) {
+                float* dst = out + 2 * ((int64_t)((by0 + row) * pr.n_u + bx0) * pr.n_w);
+                const float* src = lds_rows + (uint32_t)row * bp * (kCell / 4);
+                for (int f = lane; f < row_floats; f += kWave) {
+                    const float v = src[f];
+                    if (v != 0.0f) unsafeAtomicAdd(dst + f, v);
+                }
+            }
+            wave_lds_sync();
+        } else {
+            const int64_t lane_cell = (int64_t)(tv * pr.n_u + tu) * pr.n_w;
+#pragma unroll
+            for (int g0 = 0; g0 < NB; g0 += 8) {
+                if (g0 < count) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int j = g0 + k;
+                        const int cj = __builtin_amdgcn_readlane(in_range ? cell : -1, j);
+                        if (cj >= 0) {
+                            float* dst = out + 2 * ((int64_t)cj + lane_cell);
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cw.c[q]), j));
+                                unsafeAtomicAdd(dst + q, gv[j] * c);
+                            }
+                        }
+                    }
                 }
             }
         }
-        wave_lds_sync();
         t = t_next;
     }
     finish_launch(P.ctl, wave_oob);
@@ -775,7 +837,7 @@ hipError_t occ_degrid_v(int variant, int* n) {
 }  // namespace
 
 int degrid_variant_count() { return kNumVariants; }
-int adjoint_variant_count() { return 1; }
+int adjoint_variant_count() { return kNumVariants; }
 int degrid_variant_box_bytes(int variant) {
     return (variant >= 0 && variant < kNumVariants) ? kVariants[variant].box : -1;
 }
@@ -808,23 +870,56 @@ hipError_t degrid_kernel_occupancy(int grid_kind, int gcf_kind, int variant, int
     }
 }
 
-hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant, int blocks,
-                               hipStream_t stream) {
-    (void)variant;
-    if (gcf_kind == kGcfF32)
-        hipLaunchKernelGGL((grid_adjoint_kernel<kGcfF32>), dim3(blocks), dim3(kBlockThreads), 0, stream, p);
-    else if (gcf_kind == kGcfF16)
-        hipLaunchKernelGGL((grid_adjoint_kernel<kGcfF16>), dim3(blocks), dim3(kBlockThreads), 0, stream, p);
-    else
-        return hipErrorInvalidValue;
+template <int F, int V>
+hipError_t launch_adjoint_t(const LaunchParams& p, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((grid_adjoint_kernel<F, kVariants[V].box, kVariants[V].nb>), dim3(blocks), dim3(kBlockThreads),
+                       0, s, p);
     return hipGetLastError();
 }
 
+template <int F, int V>
+hipError_t occ_adjoint_t(int* n) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        n, grid_adjoint_kernel<F, kVariants[V].box, kVariants[V].nb>, kBlockThreads, 0);
+}
+
+template <int F>
+hipError_t launch_adjoint_v(const LaunchParams& p, int variant, int blocks, hipStream_t s) {
+    switch (variant) {
+        case 0: return launch_adjoint_t<F, 0>(p, blocks, s);
+        case 1: return launch_adjoint_t<F, 1>(p, blocks, s);
+        case 2: return launch_adjoint_t<F, 2>(p, blocks, s);
+        case 3: return launch_adjoint_t<F, 3>(p, blocks, s);
+        case 4: return launch_adjoint_t<F, 4>(p, blocks, s);
+        case 5: return launch_adjoint_t<F, 5>(p, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int F>
+hipError_t occ_adjoint_v(int variant, int* n) {
+    switch (variant) {
+        case 0: return occ_adjoint_t<F, 0>(n);
+        case 1: return occ_adjoint_t<F, 1>(n);
+        case 2: return occ_adjoint_t<F, 2>(n);
+        case 3: return occ_adjoint_t<F, 3>(n);
+        case 4: return occ_adjoint_t<F, 4>(n);
+        case 5: return occ_adjoint_t<F, 5>(n);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant, int blocks,
+                               hipStream_t stream) {
+    if (gcf_kind == kGcfF32) return launch_adjoint_v<kGcfF32>(p, variant, blocks, stream);
+    if (gcf_kind == kGcfF16) return launch_adjoint_v<kGcfF16>(p, variant, blocks, stream);
+    return hipErrorInvalidValue;
+}
+
 hipError_t adjoint_kernel_occupancy(int gcf_kind, int variant, int* n) {
-    (void)variant;
-    if (gcf_kind == kGcfF32)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, grid_adjoint_kernel<kGcfF32>, kBlockThreads, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, grid_adjoint_kernel<kGcfF16>, kBlockThreads, 0);
+    if (gcf_kind == kGcfF32) return occ_adjoint_v<kGcfF32>(variant, n);
+    if (gcf_kind == kGcfF16) return occ_adjoint_v<kGcfF16>(variant, n);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_start_cells(const Problem& pr, int64_t n, uint32_t* start, hipStream_t stream) {
