@@ -115,6 +115,8 @@ def main(argv=None):
     ap.add_argument("--input-order", action="store_true",
                     help="time the plan without the plan-time work order (degrid_plan_sort)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-patterns", action="store_true",
+                    help="skip the batched and differentiation measurements")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -230,8 +232,126 @@ def main(argv=None):
         v.pop("out", None)
     if variants:
         result["variants"] = variants
+    if not args.no_patterns:
+        del inputs, out
+        torch.cuda.empty_cache()
+        result["batched"] = bench_batched(args.steps, args.warmup, not args.no_cpu_baseline)
+        result["differentiation"] = bench_differentiation(args.steps, args.warmup, not args.no_cpu_baseline)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def bench_batched(steps, warmup, check):
+    """Eight independent problems (S in 4..64, counts log-uniform in
+    [2^8, 2^18], os in {8, 16, 32}, seed 2) in one persistent launch replayed
+    from a HIP graph, against the same eight plans launched one by one."""
+    import numpy as np
+    import torch
+    from paper_2102_12739_amd import workload as wl
+    from paper_2102_12739_amd.degrid import Batch, Plan
+    t = time.perf_counter()
+    probs = wl.batched(seed=2)
+    log(f"batched workload: {[p.n_subgrids for p in probs]} subgrids, {sum(p.n_vis for p in probs)} visibilities, "
+        f"generated in {time.perf_counter() - t:.1f}s")
+    ins = [upload_inputs(p) for p in probs]
+    outs = [torch.empty(p.n_vis, dtype=torch.complex64, device="cuda:0") for p in probs]
+    plans = []
+    t = time.perf_counter()
+    for p, i in zip(probs, ins):
+        pl = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w)
+        pl.sort(i[3])
+        plans.append(pl)
+    plan_s = time.perf_counter() - t
+    batch = Batch(plans)
+    args = [i for i in ins]
+    stream = torch.cuda.current_stream()
+    n_vis = sum(p.n_vis for p in probs)
+
+    def run_batch():
+        batch.execute(args, outs=outs, stream=stream)
+
+    def run_plain():
+        for pl, i, o in zip(plans, ins, outs):
+            pl.execute(*i, out=o, stream=stream)
+
+    res = {"workload": "batched-8-problems-S4..64-loguniform-2^8..2^18-os8/16/32", "visibilities": n_vis,
+           "problems": len(probs), "plan_and_sort_s": plan_s}
+    for name, fn in (("batch_graph", run_batch), ("separate_launches", run_plain)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[name] = {"ms_per_step": ms, "value": n_vis / (ms * 1e-3)}
+    res["speedup_batch_vs_separate"] = res["separate_launches"]["ms_per_step"] / res["batch_graph"]["ms_per_step"]
+    if check:
+        import oracle
+        run_batch()
+        torch.cuda.synchronize()
+        num = den = 0.0
+        for p, o in zip(probs, outs):
+            ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+            got = o.cpu().numpy().astype(np.complex128)
+            num += float(np.sum(np.abs(got - ref) ** 2))
+            den += float(np.sum(np.abs(ref) ** 2))
+        res["rel_l2"] = (num / den) ** 0.5
+    log(f"batched: graph {res['batch_graph']['ms_per_step']:.3f} ms, separate {res['separate_launches']['ms_per_step']:.3f} ms")
+    batch.close()
+    return res
+
+
+def bench_differentiation(steps, warmup, check):
+    """Loss ||degrid(A) - V_obs||^2 on 16 subgrids with 2^16 uniform random
+    visibilities each (seed 4); one step = forward degrid + backward (the
+    gridding adjoint through torch.autograd)."""
+    import numpy as np
+    import torch
+    from paper_2102_12739_amd import workload as wl
+    from paper_2102_12739_amd.degrid import DegridFn, Plan
+    p = wl.differentiation(seed=4)
+    sub, g_uv, g_w, uvw = upload_inputs(p)
+    plan = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w)
+    plan.sort(uvw)
+    v_obs = torch.from_numpy(wl.complex_noise(4, p.n_vis, 0.01)).to("cuda:0") + plan.execute(sub, g_uv, g_w, uvw)
+    a = (sub + torch.from_numpy(wl.perturbation(4, plan.shape, 0.1)).to("cuda:0")).requires_grad_(True)
+
+    def step():
+        a.grad = None
+        vis = DegridFn.apply(a, plan, g_uv, g_w, uvw)
+        loss = torch.sum(torch.abs(vis - v_obs) ** 2)
+        loss.backward()
+
+    out = torch.empty(p.n_vis, dtype=torch.complex64, device="cuda:0")
+    vin = torch.randn(p.n_vis, dtype=torch.complex64, device="cuda:0")
+    gout = torch.empty(plan.shape, dtype=torch.complex64, device="cuda:0")
+    res = {"workload": f"differentiation-S16-65536-uniform", "visibilities": p.n_vis}
+    for name, fn in (("forward_backward", step),
+                     ("degrid", lambda: plan.execute(sub, g_uv, g_w, uvw, out=out)),
+                     ("adjoint", lambda: plan.adjoint(vin, g_uv, g_w, uvw, out=gout))):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[name] = {"ms_per_step": ms, "value": p.n_vis / (ms * 1e-3)}
+    if check:
+        import oracle
+        step()
+        torch.cuda.synchronize()
+        a0 = a.detach().cpu().numpy()
+        r, _ = oracle.degrid(a0, p.g_uv, p.g_w, p.uvw, p.offsets)
+        ref, _ = oracle.grid(2.0 * (r - v_obs.cpu().numpy()), p.g_uv, p.g_w, p.uvw, p.offsets, plan.shape)
+        got = a.grad.cpu().numpy()
+        res["gradient_rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    log(f"differentiation: forward+backward {res['forward_backward']['ms_per_step']:.3f} ms, "
+        f"adjoint {res['adjoint']['ms_per_step']:.3f} ms")
+    return res
 
 
 if __name__ == "__main__":
