@@ -174,7 +174,34 @@ struct dg_plan_ {
     uint32_t* d_perm = nullptr;   // work order from degrid_plan_sort (nullptr: input order)
     std::vector<uint32_t> start;  // first tap per work position (from degrid_plan_sort)
     uint64_t version = 0;         // bumped when tiles or work order change
+    // owner-computes adjoint (built by degrid_plan_sort)
+    OwnerBlock* d_own_blocks = nullptr;
+    uint32_t* d_own_items = nullptr;
+    uint32_t* d_plan_start = nullptr;   // first tap per visibility index at sort time
+    int64_t* d_offsets = nullptr;
+    Ctl* d_own_ctl = nullptr;
+    QueueSpec own_q{};
+    int32_t own_grid = 0;
+    int32_t nby = 0, nbx = 0;
 };
+
+namespace {
+
+void free_owner(dg_plan_* p) {
+    if (p->d_own_blocks) (void)hipFree(p->d_own_blocks);
+    if (p->d_own_items) (void)hipFree(p->d_own_items);
+    if (p->d_plan_start) (void)hipFree(p->d_plan_start);
+    if (p->d_offsets) (void)hipFree(p->d_offsets);
+    if (p->d_own_ctl) (void)hipFree(p->d_own_ctl);
+    p->d_own_blocks = nullptr;
+    p->d_own_items = nullptr;
+    p->d_plan_start = nullptr;
+    p->d_offsets = nullptr;
+    p->d_own_ctl = nullptr;
+    p->own_grid = 0;
+}
+
+}  // namespace
 
 struct dg_batch_ {
     std::vector<dg_plan> plans;
@@ -338,6 +365,61 @@ LaunchParams params_for(const dg_plan_* p, const Problem& pr) {
 
 }  // namespace
 
+// Output-block lists for the owner-computes adjoint, from the sorted order
+// and first taps. Subgrid sides must be multiples of the block side.
+dg_status build_owner(dg_plan_* p, hipStream_t stream) {
+    free_owner(p);
+    const dg_desc& d = p->desc;
+    if (d.n_v % kOwnerBlock != 0 || d.n_u % kOwnerBlock != 0) return DG_OK;
+    const int64_t n = p->offsets.back();
+    std::vector<uint32_t> perm((size_t)n);
+    hipError_t e = hipMemcpy(perm.data(), p->d_perm, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work order)");
+    std::vector<uint32_t> start_of_vis((size_t)n);
+    for (int64_t q = 0; q < n; ++q) start_of_vis[perm[(size_t)q]] = p->start[(size_t)q];
+    BlockLists bl = build_block_lists(p->n_sub, p->offsets.data(), perm.data(), p->start.data(), d.n_v, d.n_u,
+                                      kOwnerBlock, kSupportUV);
+    const int64_t n_blocks = (int64_t)bl.offsets.size() - 1;
+    std::vector<OwnerBlock> blocks((size_t)n_blocks);
+    std::vector<int64_t> weight((size_t)n_blocks);
+    for (int64_t b = 0; b < n_blocks; ++b) {
+        const int64_t c = bl.offsets[b + 1] - bl.offsets[b];
+        if (c > 0x7FFFFFFF) return fail(DG_ERR_UNSUPPORTED, "too many visibilities on one output block");
+        blocks[(size_t)b] = OwnerBlock{bl.offsets[b], (int32_t)c, (int32_t)b};
+        weight[(size_t)b] = c + 2 * kOwnerBlock;   // visibilities plus the block's load and store
+    }
+    auto dev = [&](void** ptr, const void* src, size_t bytes, const char* what) -> dg_status {
+        hipError_t err = hipMalloc(ptr, std::max<size_t>(bytes, 16));
+        if (err != hipSuccess) { *ptr = nullptr; return hip_fail(err, what); }
+        if (bytes > 0) err = hipMemcpyAsync(*ptr, src, bytes, hipMemcpyHostToDevice, stream);
+        return err == hipSuccess ? DG_OK : hip_fail(err, what);
+    };
+    dg_status s = dev((void**)&p->d_own_blocks, blocks.data(), blocks.size() * sizeof(OwnerBlock), "owner blocks");
+    if (s == DG_OK) s = dev((void**)&p->d_own_items, bl.items.data(), bl.items.size() * sizeof(uint32_t), "owner items");
+    if (s == DG_OK) s = dev((void**)&p->d_plan_start, start_of_vis.data(), start_of_vis.size() * sizeof(uint32_t), "plan start");
+    if (s == DG_OK) s = dev((void**)&p->d_offsets, p->offsets.data(), p->offsets.size() * sizeof(int64_t), "offsets");
+    if (s == DG_OK) {
+        e = hipMalloc(&p->d_own_ctl, sizeof(Ctl));
+        if (e == hipSuccess) e = hipMemsetAsync(p->d_own_ctl, 0, sizeof(Ctl), stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) s = hip_fail(e, "owner control block");
+    }
+    if (s != DG_OK) {
+        free_owner(p);
+        return s;
+    }
+    int occ = 0;
+    e = owner_kernel_occupancy(d.gcf_dtype, &occ);
+    if (e != hipSuccess) { free_owner(p); return hip_fail(e, "occupancy query (owner)"); }
+    int n_cu = 0;
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+    p->own_q = split_queues_weighted(weight);
+    p->own_grid = blocks_for(std::max(1, n_cu * std::max(1, occ)), n_blocks);
+    p->nby = d.n_v / kOwnerBlock;
+    p->nbx = d.n_u / kOwnerBlock;
+    return DG_OK;
+}
+
 extern "C" {
 
 dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_offsets,
@@ -389,6 +471,28 @@ dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void*
     if (accumulate != 0 && accumulate != 1) return fail(DG_ERR_INVALID_ARG, "accumulate must be 0 or 1");
     if (!subgrids_out && p->n_sub > 0) return fail(DG_ERR_INVALID_ARG, "subgrids_out is NULL");
     const int64_t out_bytes = p->n_sub * (int64_t)p->desc.n_v * p->desc.n_u * p->desc.n_w * 8;
+    if (p->d_own_blocks && p->offsets.back() > 0) {
+        // owner-computes: every output block written once, then the fix-up
+        if (!vis || !g_uv || !g_w || !uvw) return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+        OwnerParams op{};
+        op.prob = problem_of(p, nullptr, g_uv, g_w, uvw, const_cast<void*>(vis), subgrids_out);
+        op.blocks = p->d_own_blocks;
+        op.items = p->d_own_items;
+        op.plan_start = p->d_plan_start;
+        op.ctl = p->d_own_ctl;
+        op.q = p->own_q;
+        op.accumulate = accumulate;
+        op.nby = p->nby;
+        op.nbx = p->nbx;
+        hipError_t e = launch_grid_owner(op, p->desc.gcf_dtype, p->own_grid, stream);
+        if (e == hipSuccess)
+            e = launch_grid_fixup(op.prob, p->d_offsets, p->n_sub, p->offsets.back(), p->d_plan_start, p->ds.ctl,
+                                  p->desc.gcf_dtype, stream);
+        if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+        p->last_stream = stream;
+        p->launched = true;
+        return DG_OK;
+    }
     if (!accumulate) {
         hipError_t e = launch_zero(subgrids_out, out_bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "zero-fill kernel launch");
@@ -485,6 +589,7 @@ dg_status degrid_plan_sort(dg_plan p, const double* uvw, hipStream_t stream) {
             (void)hipFree(p->d_perm);
             p->d_perm = nullptr;
             p->start.clear();
+            free_owner(p);
             return rebuild_tiles(p, p->n_b_req, stream);
         }
         return DG_OK;
@@ -518,6 +623,8 @@ dg_status degrid_plan_sort(dg_plan p, const double* uvw, hipStream_t stream) {
         p->start.clear();
         return hip_fail(e, "computing start cells");
     }
+    dg_status st = build_owner(p, stream);
+    if (st != DG_OK) return st;
     return rebuild_tiles(p, p->n_b_req, stream);
 }
 
@@ -534,6 +641,7 @@ dg_status degrid_destroy(dg_plan p) {
     if (!p) return DG_OK;
     (void)hipDeviceSynchronize();
     if (p->d_perm) (void)hipFree(p->d_perm);
+    free_owner(p);
     free_scratch(p->ds);
     delete p;
     return DG_OK;

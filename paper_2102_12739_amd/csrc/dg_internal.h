@@ -59,6 +59,27 @@ struct LaunchParams {
     QueueSpec q;
 };
 
+// One output block of the owner-computes adjoint and its visibility list.
+struct OwnerBlock {
+    int64_t begin;   // first entry in the item list
+    int32_t count;   // entries
+    int32_t block;   // block index (s * nby + by) * nbx + bx
+};
+static_assert(sizeof(OwnerBlock) == 16, "OwnerBlock must stay 16 bytes");
+
+constexpr int kOwnerBlock = 16;   // cells per side of an owner-computes output block
+
+struct OwnerParams {
+    Problem prob;                  // g_uv, g_w, uvw, vis (input), grid_out
+    const OwnerBlock* blocks;
+    const uint32_t* items;         // visibility indices per block
+    const uint32_t* plan_start;    // first tap (y0 << 16 | x0) per visibility at plan time
+    Ctl* ctl;
+    QueueSpec q;
+    int32_t accumulate;            // 1: add to grid_out, 0: overwrite
+    int32_t nby, nbx;              // blocks per subgrid along v and u
+};
+
 enum GridKind : int32_t { kGridC64 = 0, kGridCBF16 = 1, kGridCF16 = 2 };
 enum GcfKind : int32_t { kGcfF32 = 0, kGcfF16 = 1 };
 
@@ -68,6 +89,14 @@ hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int
 hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant, int blocks,
                                hipStream_t stream);
 hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t stream);
+// Owner-computes adjoint: every output block written once from its list.
+hipError_t launch_grid_owner(const OwnerParams& p, int gcf_kind, int blocks, hipStream_t stream);
+hipError_t owner_kernel_occupancy(int gcf_kind, int* blocks_per_cu);
+// Adds, with atomics, the visibilities whose first tap differs from the
+// plan's (those the owner pass skipped), and counts out-of-range ones into
+// ctl. n_vis visibilities of one problem; vis_offsets on the device.
+hipError_t launch_grid_fixup(const Problem& pr, const int64_t* vis_offsets, int64_t n_sub, int64_t n_vis,
+                             const uint32_t* plan_start, Ctl* ctl, int gcf_kind, hipStream_t stream);
 // tile_vis[t * kMaxNb + j] = visibility index of item j of tile t: through
 // perms[tile.problem] (a work-order permutation, or nullptr for input order)
 // at position tile.begin + j; items past the tile's count repeat its first.

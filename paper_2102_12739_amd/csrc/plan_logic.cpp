@@ -59,19 +59,56 @@ std::vector<Tile> build_tiles_fitted(int64_t n_sub, const int64_t* off, const ui
     return tiles;
 }
 
-QueueSpec split_queues(const std::vector<Tile>& tiles) {
+BlockLists build_block_lists(int64_t n_sub, const int64_t* off, const uint32_t* vis_of, const uint32_t* start,
+                             int n_v, int n_u, int block, int support) {
+    const int nby = n_v / block, nbx = n_u / block;
+    const int64_t n_blocks = n_sub * nby * nbx;
+    BlockLists bl;
+    bl.offsets.assign((size_t)n_blocks + 1, 0);
+    // blocks overlapped by the neighbourhood that starts at (x0, y0)
+    auto span = [&](int c0, int nb, int& lo, int& hi) {
+        lo = std::max(0, c0 / block);
+        hi = std::min(nb - 1, (c0 + support - 1) / block);
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<int64_t> fill;
+        if (pass == 1) {
+            for (int64_t b = 0; b < n_blocks; ++b) bl.offsets[b + 1] += bl.offsets[b];
+            bl.items.resize((size_t)bl.offsets[n_blocks]);
+            fill.assign(bl.offsets.begin(), bl.offsets.end() - 1);
+        }
+        for (int64_t s = 0; s < n_sub; ++s)
+            for (int64_t p = off[s]; p < off[s + 1]; ++p) {
+                const uint32_t st = start[p];
+                if (st == kNoStart) continue;
+                const int x0 = (int)(st & 0xFFFFu), y0 = (int)(st >> 16);
+                int bx_lo, bx_hi, by_lo, by_hi;
+                span(x0, nbx, bx_lo, bx_hi);
+                span(y0, nby, by_lo, by_hi);
+                for (int by = by_lo; by <= by_hi; ++by)
+                    for (int bx = bx_lo; bx <= bx_hi; ++bx) {
+                        const int64_t b = (s * nby + by) * nbx + bx;
+                        if (pass == 0) bl.offsets[b + 1]++;
+                        else bl.items[(size_t)fill[b]++] = vis_of[p];
+                    }
+            }
+    }
+    return bl;
+}
+
+QueueSpec split_queues_weighted(const std::vector<int64_t>& weights) {
     QueueSpec q{};
-    const int64_t n_tiles = (int64_t)tiles.size();
-    const int nq = (int)std::min<int64_t>(kMaxQueues, std::max<int64_t>(1, n_tiles));
+    const int64_t n = (int64_t)weights.size();
+    const int nq = (int)std::min<int64_t>(kMaxQueues, std::max<int64_t>(1, n));
     q.n_queues = nq;
     int64_t total = 0;
-    for (const Tile& t : tiles) total += t.count;
+    for (int64_t w : weights) total += w;
     int64_t acc = 0;
     int cur = 0;
     q.begin[0] = 0;
-    for (int64_t i = 0; i < n_tiles && cur < nq - 1; ++i) {
-        acc += tiles[(size_t)i].count;
-        // close queue 'cur' once it holds its share of the visibilities
+    for (int64_t i = 0; i < n && cur < nq - 1; ++i) {
+        acc += weights[(size_t)i];
+        // close queue 'cur' once it holds its share of the weight
         if (acc * nq >= total * (int64_t)(cur + 1)) {
             q.end[cur] = (int32_t)(i + 1);
             ++cur;
@@ -79,10 +116,16 @@ QueueSpec split_queues(const std::vector<Tile>& tiles) {
         }
     }
     for (int c = cur; c < nq; ++c) {
-        if (c > cur) q.begin[c] = (int32_t)n_tiles;
-        q.end[c] = (int32_t)n_tiles;
+        if (c > cur) q.begin[c] = (int32_t)n;
+        q.end[c] = (int32_t)n;
     }
     return q;
+}
+
+QueueSpec split_queues(const std::vector<Tile>& tiles) {
+    std::vector<int64_t> w(tiles.size());
+    for (size_t i = 0; i < tiles.size(); ++i) w[i] = tiles[i].count;
+    return split_queues_weighted(w);
 }
 
 }  // namespace dg

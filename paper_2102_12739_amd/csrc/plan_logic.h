@@ -53,9 +53,27 @@ std::vector<Tile> build_tiles_fitted(int64_t n_sub, const int64_t* off, const ui
                                      int support, int64_t cap_cells, int min_fit, uint16_t problem,
                                      int pad_to = 0);
 
+// Output blocks of the owner-computes adjoint: block b of subgrid s covers
+// cells [by * B, by * B + B) x [bx * B, bx * B + B) (b = (s * nby + by) * nbx + bx,
+// nby = n_v / B, nbx = n_u / B). items[offsets[b] .. offsets[b+1]) are the
+// visibilities whose W x W neighbourhood overlaps the block: first tap
+// (x0, y0) with x0 in [bx * B - W + 1, bx * B + B - 1], likewise y0.
+// vis_of[p] is the visibility at work position p, start[p] its first tap
+// (y0 << 16 | x0) or kNoStart (never listed). Within a block, items keep
+// work order.
+struct BlockLists {
+    std::vector<int64_t> offsets;   // [n_blocks + 1]
+    std::vector<uint32_t> items;    // visibility indices
+};
+BlockLists build_block_lists(int64_t n_sub, const int64_t* off, const uint32_t* vis_of, const uint32_t* start,
+                             int n_v, int n_u, int block, int support);
+
 // Split a tile list into up to kMaxQueues contiguous queues holding about
 // equal numbers of visibilities (empty queues only when there are fewer
 // tiles than queues).
 QueueSpec split_queues(const std::vector<Tile>& tiles);
+
+// The same split for work items of the given weights.
+QueueSpec split_queues_weighted(const std::vector<int64_t>& weights);
 
 }  // namespace dg

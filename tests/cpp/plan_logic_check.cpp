@@ -3,6 +3,8 @@
 //   plan_logic_check <nb> <count>...                    fixed-size tiles
 //   plan_logic_check fitted <nb> <cap> <min_fit> <pad_to> <file> tiles cut to fit a box;
 //       <file>: line 1 = per-subgrid counts, line 2 = start word per visibility
+//   plan_logic_check blocks <n_v> <n_u> <block> <file> output-block lists;
+//       <file>: counts, start words, visibility index per work position
 #include "plan_logic.h"
 
 #include <cstdio>
@@ -28,6 +30,32 @@ static void print(const std::vector<dg::Tile>& tiles) {
 
 int main(int argc, char** argv) {
     if (argc < 2) return 2;
+    if (std::strcmp(argv[1], "blocks") == 0) {
+        if (argc != 6) return 2;
+        const int n_v = std::atoi(argv[2]), n_u = std::atoi(argv[3]), block = std::atoi(argv[4]);
+        std::ifstream f(argv[5]);
+        std::string l1, l2, l3;
+        std::getline(f, l1);
+        std::getline(f, l2);
+        std::getline(f, l3);
+        std::vector<int64_t> off(1, 0);
+        std::istringstream c(l1), st(l2), vs(l3);
+        long long x;
+        while (c >> x) off.push_back(off.back() + x);
+        std::vector<uint32_t> start, vis;
+        unsigned long long w;
+        while (st >> w) start.push_back((uint32_t)w);
+        while (vs >> w) vis.push_back((uint32_t)w);
+        if ((int64_t)start.size() != off.back() || vis.size() != start.size()) return 3;
+        dg::BlockLists bl = dg::build_block_lists((int64_t)off.size() - 1, off.data(), vis.data(), start.data(),
+                                                  n_v, n_u, block, 8);
+        std::printf("{\"offsets\": [");
+        for (size_t i = 0; i < bl.offsets.size(); ++i) std::printf("%s%lld", i ? ", " : "", (long long)bl.offsets[i]);
+        std::printf("], \"items\": [");
+        for (size_t i = 0; i < bl.items.size(); ++i) std::printf("%s%u", i ? ", " : "", bl.items[i]);
+        std::printf("]}\n");
+        return 0;
+    }
     if (std::strcmp(argv[1], "fitted") == 0) {
         if (argc != 7) return 2;
         const int nb = std::atoi(argv[2]);

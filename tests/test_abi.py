@@ -255,3 +255,44 @@ def test_fitted_tiles_cover_fit_the_box_and_are_greedy(plan_logic_exe, tmp_path,
                 k += 1
             assert k < min_fit
     assert np.all(covered == 1)
+
+
+@pytest.mark.parametrize("seed,block", [(0, 16), (1, 32), (2, 8)])
+def test_block_lists_hold_exactly_the_overlapping_visibilities(plan_logic_exe, tmp_path, seed, block):
+    """Output-block lists of the owner-computes adjoint: every (visibility,
+    block) pair whose 8x8 neighbourhood overlaps the block appears once, in
+    work order, and nothing else does."""
+    rng = np.random.default_rng(seed)
+    n_v, n_u, no_start = 48, 64, 0xFFFFFFFF
+    counts = [int(c) for c in rng.integers(0, 300, 4)] + [0, 5]
+    n = sum(counts)
+    starts = []
+    for _ in range(n):
+        if rng.random() < 0.05:
+            starts.append(no_start)
+        else:
+            x0, y0 = int(rng.integers(0, n_u - 7)), int(rng.integers(0, n_v - 7))
+            starts.append((y0 << 16) | x0)
+    vis = [int(v) for v in rng.permutation(n)]
+    f = tmp_path / "blocks.txt"
+    f.write_text("\n".join(" ".join(map(str, a)) for a in (counts, starts, vis)) + "\n")
+    r = subprocess.run([plan_logic_exe, "blocks", str(n_v), str(n_u), str(block), str(f)],
+                       capture_output=True, text=True, check=True)
+    out = json.loads(r.stdout)
+    nby, nbx = n_v // block, n_u // block
+    off = np.concatenate([[0], np.cumsum(counts)])
+    expect = {}
+    for s in range(len(counts)):
+        for p in range(off[s], off[s + 1]):
+            if starts[p] == no_start:
+                continue
+            x0, y0 = starts[p] & 0xFFFF, starts[p] >> 16
+            for by in range(nby):
+                for bx in range(nbx):
+                    if x0 + 7 >= bx * block and x0 < bx * block + block and \
+                            y0 + 7 >= by * block and y0 < by * block + block:
+                        expect.setdefault((s * nby + by) * nbx + bx, []).append(vis[p])
+    offsets, items = out["offsets"], out["items"]
+    assert len(offsets) == len(counts) * nby * nbx + 1
+    for b in range(len(offsets) - 1):
+        assert items[offsets[b]:offsets[b + 1]] == expect.get(b, []), b
