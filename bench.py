@@ -30,7 +30,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_VIS = {"c64": 2048 + 256 + 16 + 24 + 8, "cbf16": 1024 + 128 + 8 + 24 + 8, "cf16": 1024 + 128 + 8 + 24 + 8}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "degrid_fp32_paper_scale_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2102_12739_amd", "csrc", "degrid_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_12739_amd", "csrc", f)
+                  for f in ("degrid_kernels.hip", "dg_device.h", "dg_internal.h")]
+FLUSH_BYTES = 1 << 30     # written between launches of the cold-cache timing
 
 
 def log(*a):
@@ -38,8 +40,12 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256[:16] of the degrid kernel's source and the device code it includes."""
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -102,6 +108,81 @@ def copy_calibration(n_bytes=1 << 30):
         b.copy_(a)
     torch.cuda.synchronize()
     log(f"copy calibration: 3 copies of {n_bytes} bytes")
+
+
+def percentiles(ms):
+    import numpy as np
+    a = np.asarray(ms, dtype=np.float64)
+    return {"p10": float(np.percentile(a, 10)), "median": float(np.median(a)), "p90": float(np.percentile(a, 90)),
+            "n": int(a.size)}
+
+
+def launch_times(fn, n, flush=None):
+    """Duration of n single launches (HIP events around each), in ms; flush()
+    runs untimed before each launch."""
+    import torch
+    stream = torch.cuda.current_stream()
+    out = []
+    for _ in range(n):
+        if flush is not None:
+            flush()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out
+
+
+def copy_bandwidth(n_bytes=1 << 30, reps=10):
+    """Device-to-device copy rate (read + write bytes per second) on this GPU."""
+    import torch
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    ms = percentiles(launch_times(lambda: b.copy_(a), reps))["median"]
+    del a, b
+    return 2.0 * n_bytes / (ms * 1e-3) / 1e9
+
+
+def compulsory_bytes(p, elem_bytes):
+    """Bytes a launch must move at least: every subgrid cell inside some
+    in-range visibility's 8 x 8 (x 4 w) neighbourhood once, plus the
+    coordinates and output of every visibility and both tables. Host-side
+    footprint count (start cell = floor(c) - 3 along u and v)."""
+    import numpy as np
+    cells = 0
+    for s in range(p.n_subgrids):
+        lo, hi = int(p.offsets[s]), int(p.offsets[s + 1])
+        if hi == lo:
+            continue
+        c = p.uvw[lo:hi]
+        x0 = np.floor(c[:, 0]).astype(np.int64) - 3
+        y0 = np.floor(c[:, 1]).astype(np.int64) - 3
+        z0 = np.floor(c[:, 2]).astype(np.int64) - 1
+        ok = (x0 >= 0) & (x0 <= p.n_u - 8) & (y0 >= 0) & (y0 <= p.n_v - 8) & (z0 >= 0) & (z0 <= p.n_w - 4)
+        starts = np.zeros((p.n_v + 8, p.n_u + 8), dtype=np.int64)
+        np.add.at(starts, (y0[ok] + 8, x0[ok] + 8), 1)
+        # cell (y, x) is covered when some start lies in [y-7, y] x [x-7, x]
+        ii = np.cumsum(np.cumsum(starts, axis=0), axis=1)
+        box = ii[8:, 8:] - ii[:-8, 8:] - ii[8:, :-8] + ii[:-8, :-8]
+        cells += int(np.count_nonzero(box))
+    tables = p.g_uv.size * (4 if elem_bytes == 8 else 2) + p.g_w.size * (4 if elem_bytes == 8 else 2)
+    return cells * p.n_w * elem_bytes + 32 * p.n_vis + tables
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main(argv=None):
@@ -181,6 +262,29 @@ def main(argv=None):
                      "kernel": "degrid_kernel<c64,f32>", "bytes_per_vis": BYTES_PER_VIS["c64"],
                      "kernel_ms": ms_kernel},
     }
+    # Per-launch distribution, back to back (warm) and after writing 1 GiB
+    # between launches (cold L2 and Infinity Cache), plus what the memory
+    # system does on a plain copy and the bytes a launch cannot avoid.
+    flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    run = lambda: plan.execute(*inputs, out=out)   # noqa: E731
+    warm = percentiles(launch_times(run, 50))
+    cold = percentiles(launch_times(run, 20, flush=lambda: flush_buf.fill_(1.0)))
+    del flush_buf
+    torch.cuda.empty_cache()
+    comp = compulsory_bytes(p, 8)
+    result["timing"] = {
+        "warm_kernel_ms": warm, "cold_kernel_ms": cold,
+        "warm_median_value": p.n_vis / (warm["median"] * 1e-3),
+        "cold_median_value": p.n_vis / (cold["median"] * 1e-3),
+        "cold_median_roofline_frac": bytes_launch / (cold["median"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+    }
+    result["roofline"]["copy_gbs"] = copy_bandwidth()
+    result["roofline"]["compulsory_bytes_per_launch"] = comp
+    result["roofline"]["compulsory_gbs_cold"] = comp / (cold["median"] * 1e-3) / 1e9
+    result["device"] = {"name": torch.cuda.get_device_name(0),
+                        "compute_units": torch.cuda.get_device_properties(0).multi_processor_count}
+    log(f"warm median {warm['median']:.4f} ms, cold median {cold['median']:.4f} ms, "
+        f"copy {result['roofline']['copy_gbs']:.0f} GB/s, compulsory {comp / 1e9:.3f} GB/launch")
     if tune_s is not None:
         result["config"]["tune_s"] = tune_s
     result["config"]["work_order"] = ("input order" if args.input_order else
@@ -212,16 +316,32 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         import oracle
         a64 = p.subgrids.astype(np.complex128)
+        cores = len(os.sched_getaffinity(0))
+        threads0 = oracle.num_threads()
+        runs = []
+        for _ in range(3):
+            t = time.perf_counter()
+            ref, _ = oracle.degrid(a64, p.g_uv, p.g_w, p.uvw, p.offsets)
+            runs.append(time.perf_counter() - t)
+        cpu_s = sorted(runs)[1]
+        # one thread, on the first eight subgrids (about 1/8 of the work)
+        n8 = int(p.offsets[8])
+        oracle.set_num_threads(1)
         t = time.perf_counter()
-        ref, _ = oracle.degrid(a64, p.g_uv, p.g_w, p.uvw, p.offsets)
-        cpu_s = time.perf_counter() - t
+        oracle.degrid(a64[:8], p.g_uv, p.g_w, p.uvw[:n8], p.offsets[:9])
+        one_s = time.perf_counter() - t
+        oracle.set_num_threads(threads0)
         got = out.cpu().numpy().astype(np.complex128)
         rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         result["cpu_baseline"] = {"value": p.n_vis / cpu_s, "unit": "visibilities/s",
-                                  "cores": oracle.num_threads(), "kind": "oracle",
+                                  "cores": threads0, "kind": "oracle",
                                   "sample": f"the whole workload ({p.n_vis} visibilities), FP64 C oracle, "
-                                            f"one run of {cpu_s:.2f} s"}
+                                            f"median of 3 runs ({cpu_s:.3f} s) on {threads0} OpenMP threads",
+                                  "one_thread_value": n8 / one_s,
+                                  "one_thread_sample": f"subgrids 0-7 ({n8} visibilities), one run of {one_s:.2f} s",
+                                  "host_cores": cores, "cpu_model": cpu_model()}
         result["rel_l2"] = rel
+        result["max_abs"] = float(np.max(np.abs(got - ref)))
         for gdt, v in variants.items():
             deq = wl.storage_to_complex128(wl.complex_to_storage(p.subgrids, gdt), gdt)
             ref_q, _ = oracle.degrid(deq, p.g_uv.astype(np.float16), p.g_w.astype(np.float16), p.uvw, p.offsets)
@@ -235,6 +355,7 @@ def main(argv=None):
     if not args.no_patterns:
         del inputs, out
         torch.cuda.empty_cache()
+        result["latency"] = bench_latency()
         result["batched"] = bench_batched(args.steps, args.warmup, not args.no_cpu_baseline)
         result["differentiation"] = bench_differentiation(args.steps, args.warmup, not args.no_cpu_baseline)
     print(json.dumps(result), flush=True)
@@ -306,17 +427,29 @@ def bench_batched(steps, warmup, check):
 def bench_differentiation(steps, warmup, check):
     """Loss ||degrid(A) - V_obs||^2 on 16 subgrids with 2^16 uniform random
     visibilities each (seed 4); one step = forward degrid + backward (the
-    gridding adjoint through torch.autograd)."""
+    gridding adjoint through torch.autograd). Also checks, on the GPU
+    outputs with float64 sums on the host, the adjoint identity
+    <degrid A, V> = <A, grid V> and the gradient against central
+    differences (exact for a quadratic loss) at 16 random points."""
     import numpy as np
     import torch
     from paper_2102_12739_amd import workload as wl
     from paper_2102_12739_amd.degrid import DegridFn, Plan
     p = wl.differentiation(seed=4)
+    dev = torch.device("cuda:0")
     sub, g_uv, g_w, uvw = upload_inputs(p)
     plan = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w)
     plan.sort(uvw)
-    v_obs = torch.from_numpy(wl.complex_noise(4, p.n_vis, 0.01)).to("cuda:0") + plan.execute(sub, g_uv, g_w, uvw)
-    a = (sub + torch.from_numpy(wl.perturbation(4, plan.shape, 0.1)).to("cuda:0")).requires_grad_(True)
+    noise = wl.complex_noise(4, p.n_vis, 0.01)
+    if check:
+        import oracle
+        v_true, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+        v_obs_host = (v_true + noise).astype(np.complex64)
+    else:
+        v_obs_host = (plan.execute(sub, g_uv, g_w, uvw).cpu().numpy() + noise).astype(np.complex64)
+    v_obs = torch.from_numpy(v_obs_host).to(dev)
+    a_host = (p.subgrids + wl.perturbation(4, plan.shape, 0.1)).astype(np.complex64)
+    a = torch.from_numpy(a_host).to(dev).requires_grad_(True)
 
     def step():
         a.grad = None
@@ -324,10 +457,12 @@ def bench_differentiation(steps, warmup, check):
         loss = torch.sum(torch.abs(vis - v_obs) ** 2)
         loss.backward()
 
-    out = torch.empty(p.n_vis, dtype=torch.complex64, device="cuda:0")
-    vin = torch.randn(p.n_vis, dtype=torch.complex64, device="cuda:0")
-    gout = torch.empty(plan.shape, dtype=torch.complex64, device="cuda:0")
-    res = {"workload": f"differentiation-S16-65536-uniform", "visibilities": p.n_vis}
+    out = torch.empty(p.n_vis, dtype=torch.complex64, device=dev)
+    vin = torch.from_numpy(wl.complex_noise(5, p.n_vis, 1.0).astype(np.complex64)).to(dev)
+    gout = torch.empty(plan.shape, dtype=torch.complex64, device=dev)
+    res = {"workload": "differentiation-S16-65536-uniform", "visibilities": p.n_vis,
+           "v_obs": "oracle degrid of the true subgrids + N(0, 0.01^2) per component" if check
+           else "GPU degrid of the true subgrids + N(0, 0.01^2) per component"}
     for name, fn in (("forward_backward", step),
                      ("degrid", lambda: plan.execute(sub, g_uv, g_w, uvw, out=out)),
                      ("adjoint", lambda: plan.adjoint(vin, g_uv, g_w, uvw, out=gout))):
@@ -340,17 +475,101 @@ def bench_differentiation(steps, warmup, check):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
         res[name] = {"ms_per_step": ms, "value": p.n_vis / (ms * 1e-3)}
+    res["adjoint"]["achieved_gbs"] = BYTES_PER_VIS["c64"] * p.n_vis / (res["adjoint"]["ms_per_step"] * 1e-3) / 1e9
+
+    # adjoint identity
+    fwd = plan.execute(a.detach(), g_uv, g_w, uvw).cpu().numpy().astype(np.complex128)
+    adj = plan.adjoint(vin, g_uv, g_w, uvw).cpu().numpy().astype(np.complex128)
+    v64 = vin.cpu().numpy().astype(np.complex128)
+    lhs = np.vdot(fwd, v64)
+    rhs = np.vdot(a_host.astype(np.complex128), adj)
+    res["adjoint_identity_rel"] = float(abs(lhs - rhs) / (np.linalg.norm(fwd) * np.linalg.norm(v64)))
+
+    # central differences, h = 1 (exact for the quadratic loss), termwise in float64
+    step()
+    torch.cuda.synchronize()
+    grad = a.grad.detach().reshape(-1).cpu().numpy()
+    rng = np.random.default_rng(40)
+    points = rng.choice(grad.size, size=16, replace=False)
+    vo = v_obs_host.astype(np.complex128)
+    worst = 0.0
+    a0 = a.detach()
+    flat = a0.view(-1)
+    for idx in points:
+        keep = flat[int(idx)].clone()
+        for part, e in (("re", 1.0), ("im", 1.0j)):
+            rs = []
+            for sign in (1.0, -1.0):
+                flat[int(idx)] = keep + sign * e
+                r = plan.execute(a0, g_uv, g_w, uvw).cpu().numpy().astype(np.complex128) - vo
+                rs.append(r)
+            flat[int(idx)] = keep
+            fd = float(np.sum(np.abs(rs[0]) ** 2 - np.abs(rs[1]) ** 2)) / 2.0
+            g = float(grad[idx].real if part == "re" else grad[idx].imag)
+            worst = max(worst, abs(fd - g))
+    scale = float(np.max(np.abs(grad)))
+    res["finite_difference"] = {"points": 16, "components": 32, "h": 1.0,
+                                "max_abs_err": worst, "max_abs_err_over_max_grad": worst / scale}
     if check:
         import oracle
-        step()
-        torch.cuda.synchronize()
-        a0 = a.detach().cpu().numpy()
-        r, _ = oracle.degrid(a0, p.g_uv, p.g_w, p.uvw, p.offsets)
-        ref, _ = oracle.grid(2.0 * (r - v_obs.cpu().numpy()), p.g_uv, p.g_w, p.uvw, p.offsets, plan.shape)
+        r, _ = oracle.degrid(a_host, p.g_uv, p.g_w, p.uvw, p.offsets)
+        ref, _ = oracle.grid(2.0 * (r - vo), p.g_uv, p.g_w, p.uvw, p.offsets, plan.shape)
         got = a.grad.cpu().numpy()
         res["gradient_rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     log(f"differentiation: forward+backward {res['forward_backward']['ms_per_step']:.3f} ms, "
-        f"adjoint {res['adjoint']['ms_per_step']:.3f} ms")
+        f"adjoint {res['adjoint']['ms_per_step']:.3f} ms, identity {res['adjoint_identity_rel']:.2e}, "
+        f"fd {res['finite_difference']['max_abs_err_over_max_grad']:.2e}")
+    return res
+
+
+def bench_latency(launches=1000, replays=5):
+    """The small case: 2 subgrids of 512 x 512 x 4 with 1024 visibilities
+    each on a folded line (seed 0). A launch lasts microseconds, so this is a
+    latency figure: 1000 launches captured in one HIP graph and replayed
+    (per-launch time), beside the same 1000 launches issued one by one."""
+    import torch
+    from paper_2102_12739_amd import workload as wl
+    from paper_2102_12739_amd.degrid import Plan
+    p = wl.plain_line(seed=0)
+    ins = upload_inputs(p)
+    plan = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w)
+    plan.sort(ins[3])
+    ref = plan.execute(*ins)
+    out = torch.empty_like(ref)
+    torch.cuda.synchronize()
+    cur = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(cur)
+    for _ in range(launches):
+        plan.execute(*ins, out=out, stream=cur)
+    e1.record(cur)
+    e1.synchronize()
+    eager_us = e0.elapsed_time(e1) * 1e3 / launches
+    side = torch.cuda.Stream()
+    side.wait_stream(cur)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for _ in range(launches):
+            plan.execute(*ins, out=out, stream=side)
+    torch.cuda.synchronize()
+    per = []
+    same = True
+    for _ in range(replays):
+        out.zero_()
+        torch.cuda.synchronize()
+        e0.record(cur)
+        g.replay()
+        e1.record(cur)
+        e1.synchronize()
+        per.append(e0.elapsed_time(e1) * 1e3 / launches)
+        same = same and bool(torch.equal(out, ref))
+    del g
+    res = {"workload": f"plain-line-S2-1024 ({p.n_vis} visibilities)", "launches": launches,
+           "graph_us_per_launch": percentiles(per), "eager_us_per_launch": eager_us,
+           "graph_replays_match_eager": same,
+           "label": "latency (launch-bound: the work is a few microseconds)"}
+    log(f"latency: graph {res['graph_us_per_launch']['median']:.2f} us/launch, eager {eager_us:.2f} us/launch")
     return res
 
 

@@ -58,12 +58,19 @@ def _load():
     lib.oracle_grid.restype = i64
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = i32
+    lib.oracle_set_num_threads.argtypes = [i32]
+    lib.oracle_set_num_threads.restype = None
     _lib = lib
     return lib
 
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle calls (for timing on a chosen core count)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def _f64(a) -> np.ndarray:

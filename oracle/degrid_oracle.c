@@ -173,3 +173,13 @@ int32_t oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the threads later parallel regions of the oracle use (timing only). */
+void oracle_set_num_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads((int)n);
+#else
+    (void)n;
+#endif
+}

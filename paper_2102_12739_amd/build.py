@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdegrid.so")
-SOURCES = [os.path.join(CSRC, "degrid_kernels.hip"), os.path.join(CSRC, "degrid_api.cpp"),
+SOURCES = [os.path.join(CSRC, "degrid_kernels.hip"), os.path.join(CSRC, "grid_kernels.hip"),
+           os.path.join(CSRC, "degrid_api.cpp"),
            os.path.join(CSRC, "plan_logic.cpp"), os.path.join(CSRC, "plan_sort.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1,0 +1,368 @@
+// Device-side pieces shared by the degridding and gridding kernels on
+// gfx950: buffer resources, the tile queue, storage types, the coordinate
+// stage (Section 2: start point and oversampled table positions), the
+// cross-lane reduction and scalar-cache views of read-only data.
+#pragma once
+
+#include "dg_internal.h"
+
+#include <hip/hip_fp16.h>
+
+namespace dg {
+namespace {
+
+constexpr int32_t kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit dwords (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// XCD the wavefront runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ int xcc_id() {
+    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & 7);
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Copy of a value that the compiler knows to be the same on every lane (it
+// lives in scalar registers). Used for the per-tile descriptors loaded from
+// memory, so that addresses and buffer resources built from them stay scalar.
+template <class T>
+__device__ __forceinline__ T uniform_copy(const T& x) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized types only");
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, &x, sizeof(T));
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) w[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)w[i]);
+    T y;
+    __builtin_memcpy(&y, w, sizeof(T));
+    return y;
+}
+
+// Orders this wavefront's LDS accesses around a hand-off between its lanes.
+// LDS operations of one wavefront execute in order; this keeps the compiler
+// from moving accesses across the hand-off.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// Tile queue
+// ---------------------------------------------------------------------------
+
+struct QueueState {
+    int q;       // queue currently drained
+    int tried;   // queues found empty so far
+};
+
+// Next tile for this wavefront, or -1 once every queue is empty. A queue
+// found empty is left for the next one (at most n_queues probes at the end).
+__device__ __forceinline__ int pop_tile(const QueueSpec& qs, Ctl* ctl, QueueState& st) {
+    while (st.tried < qs.n_queues) {
+        uint32_t idx = 0;
+        if (lane_id() == 0) idx = atomicAdd(&ctl->cursor[st.q].v[0], 1u);
+        idx = (uint32_t)uniform((int)idx);
+        const int t = qs.begin[st.q] + (int)idx;
+        if (t < qs.end[st.q]) return t;
+        st.q = (st.q + 1 == qs.n_queues) ? 0 : st.q + 1;
+        st.tried++;
+    }
+    return -1;
+}
+
+// Adds this wavefront's out-of-range count; the last workgroup of the launch
+// publishes the launch total and resets cursors and counters for the next.
+__device__ __forceinline__ void finish_launch(Ctl* ctl, uint32_t wave_oob) {
+    auto* oob = reinterpret_cast<unsigned long long*>(&ctl->oob.v[0]);
+    if (lane_id() == 0 && wave_oob != 0u) atomicAdd(&oob[0], (unsigned long long)wave_oob);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(&ctl->done.v[0], 1u);
+        if (prev == gridDim.x - 1) {
+            __threadfence();
+            const unsigned long long total = atomicExch(&oob[0], 0ull);
+            atomicExch(&oob[1], total);
+            for (int q = 0; q < kMaxQueues; ++q) atomicExch(&ctl->cursor[q].v[0], 0u);
+            atomicExch(&ctl->done.v[0], 0u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Storage types
+// ---------------------------------------------------------------------------
+
+template <int G> struct GridTraits;
+template <> struct GridTraits<kGridC64> {    // complex float32
+    static constexpr uint32_t kElemBytes = 8;
+    static constexpr int kWords = 8;         // 4 w values x (re, im)
+};
+template <> struct GridTraits<kGridCBF16> {  // complex bfloat16
+    static constexpr uint32_t kElemBytes = 4;
+    static constexpr int kWords = 4;
+};
+template <> struct GridTraits<kGridCF16> {   // complex float16
+    static constexpr uint32_t kElemBytes = 4;
+    static constexpr int kWords = 4;
+};
+// bytes of one (v, u) cell: its 4 w values
+template <int G> constexpr uint32_t kCellBytes = GridTraits<G>::kElemBytes * kSupportW;
+
+template <int G>
+__device__ __forceinline__ void load_w4(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                        uint32_t (&raw)[GridTraits<G>::kWords]) {
+    if constexpr (G == kGridC64) {
+        auto a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        auto b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0);
+        raw[0] = a[0]; raw[1] = a[1]; raw[2] = a[2]; raw[3] = a[3];
+        raw[4] = b[0]; raw[5] = b[1]; raw[6] = b[2]; raw[7] = b[3];
+    } else {
+        auto a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        raw[0] = a[0]; raw[1] = a[1]; raw[2] = a[2]; raw[3] = a[3];
+    }
+}
+
+// Widen the 4 w values of one tap to float32 (re[t], im[t]).
+template <int G>
+__device__ __forceinline__ void widen_w4(const uint32_t (&raw)[GridTraits<G>::kWords],
+                                         float (&re)[4], float (&im)[4]) {
+    if constexpr (G == kGridC64) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            re[t] = __uint_as_float(raw[2 * t]);
+            im[t] = __uint_as_float(raw[2 * t + 1]);
+        }
+    } else if constexpr (G == kGridCBF16) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            re[t] = __uint_as_float(raw[t] << 16);
+            im[t] = __uint_as_float(raw[t] & 0xFFFF0000u);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const __half2 h = __builtin_bit_cast(__half2, raw[t]);
+            re[t] = __low2float(h);
+            im[t] = __high2float(h);
+        }
+    }
+}
+
+template <int F> struct GcfTraits;
+template <> struct GcfTraits<kGcfF32> { static constexpr uint32_t kBytes = 4; };
+template <> struct GcfTraits<kGcfF16> { static constexpr uint32_t kBytes = 2; };
+
+template <int F>
+__device__ __forceinline__ float load_gcf_rsrc(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (F == kGcfF32) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    } else {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        return __half2float(__builtin_bit_cast(__half, h));
+    }
+}
+
+template <int F>
+__device__ __forceinline__ float load_gcf(const void* table, int64_t idx) {
+    if constexpr (F == kGcfF32) {
+        return static_cast<const float*>(table)[idx];
+    } else {
+        return __half2float(static_cast<const __half*>(table)[idx]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coordinate stage (Section 2: start point g and oversampled GCF positions)
+// ---------------------------------------------------------------------------
+
+// Start cell offset (first tap, inside its subgrid) and table positions of
+// visibility i. Per axis k = floor(c * os) in float64, which is exact for a
+// power-of-two os; the cell is k / os, the oversample index k mod os, and the
+// first tap sits W/2 - 1 cells below the cell. Returns false when the
+// neighbourhood leaves the subgrid or the coordinate is not finite.
+__device__ __forceinline__ bool coords_from(const Problem& pr, double u, double v, double w, int32_t& cell,
+                                            int32_t& tab, int32_t& ow, int32_t& x_start, int32_t& y_start) {
+    const bool ok = (u >= 3.0) & (u < pr.hi_u) & (v >= 3.0) & (v < pr.hi_v) &
+                    (w >= 1.0) & (w < pr.hi_w);
+    if (!ok) return false;
+    const int os_uv = 1 << pr.log2_os_uv;
+    const int os_w = 1 << pr.log2_os_w;
+    const int ku = (int)(u * (double)os_uv);   // non-negative: truncation is floor
+    const int kv = (int)(v * (double)os_uv);
+    const int kw = (int)(w * (double)os_w);
+    const int x0 = (ku >> pr.log2_os_uv) - (kSupportUV / 2 - 1);
+    const int y0 = (kv >> pr.log2_os_uv) - (kSupportUV / 2 - 1);
+    const int z0 = (kw >> pr.log2_os_w) - (kSupportW / 2 - 1);
+    const int ou = ku & (os_uv - 1);
+    const int ov = kv & (os_uv - 1);
+    ow = kw & (os_w - 1);
+    cell = (y0 * pr.n_u + x0) * pr.n_w + z0;
+    tab = ((ov << pr.log2_os_uv) + ou) * (kSupportUV * kSupportUV);
+    x_start = x0;
+    y_start = y0;
+    return true;
+}
+
+__device__ __forceinline__ bool vis_coords(const Problem& pr, int64_t i, int32_t& cell,
+                                           int32_t& tab, int32_t& ow, int32_t& x_start, int32_t& y_start) {
+    const double* c = pr.uvw + 3 * i;
+    return coords_from(pr, c[0], c[1], c[2], cell, tab, ow, x_start, y_start);
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane reduction of eight visibilities
+// ---------------------------------------------------------------------------
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppQuadXor1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kDppRowRor8 = 0x128;       // rotate by 8 within 16 lanes (= lane xor 8)
+constexpr int kDppRowHalfMirror = 0x141; // lane j <-> 7 - j within 8 lanes
+
+// x <- x + (x of the lane 32 away) for the half that keeps x, and the same
+// for y on the other half: after the swap, lanes 0-31 hold x's pair sums and
+// lanes 32-63 hold y's.
+__device__ __forceinline__ float swap_add32(float x, float y) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Same with rows of 16 lanes: rows 0 and 2 keep x's sums, rows 1 and 3 y's.
+__device__ __forceinline__ float swap_add16(float x, float y) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// In: p[k] = this lane's partial sum for visibility k (k = 0..7).
+// Out: p[0] on lane l = full 64-lane sum for visibility l >> 3.
+__device__ __forceinline__ void reduce8(float (&p)[8]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = swap_add32(p[k], p[k + 4]);   // vis k + 4*bit5
+#pragma unroll
+    for (int k = 0; k < 2; ++k) p[k] = swap_add16(p[k], p[k + 2]);   // + 2*bit4
+    const bool hi = (lane_id() & 8) != 0;
+    const float keep = hi ? p[1] : p[0];
+    const float give = hi ? p[0] : p[1];
+    float s = keep + dpp<kDppRowRor8>(give);                           // + bit3
+    s += dpp<kDppRowHalfMirror>(s);
+    s += dpp<kDppQuadXor2>(s);
+    s += dpp<kDppQuadXor1>(s);
+    p[0] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Degrid kernel
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int wave_min(int x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x = min(x, __shfl_xor(x, m));
+    return x;
+}
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x = max(x, __shfl_xor(x, m));
+    return x;
+}
+
+// Scalar-cache view of read-only data: loads through it with a wave-uniform
+// address become scalar loads.
+typedef const __attribute__((address_space(4))) float* ConstF32Ptr;
+typedef const __attribute__((address_space(4))) uint32_t* ConstU32Ptr;
+typedef const __attribute__((address_space(4))) Tile* ConstTilePtr;
+typedef const __attribute__((address_space(4))) Problem* ConstProblemPtr;
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ Tile load_tile(const Tile* tiles, int t) {
+    const ConstTilePtr p = (ConstTilePtr)uniform_u64((uint64_t)tiles) + t;
+    Tile x;
+    x.begin = p->begin;
+    x.sub = p->sub;
+    x.count = p->count;
+    x.problem = p->problem;
+    return x;
+}
+
+// The fields of a batch problem the degrid kernel uses, read through the
+// scalar cache.
+__device__ __forceinline__ Problem load_problem(const Problem* probs, int i) {
+    const ConstProblemPtr p = (ConstProblemPtr)uniform_u64((uint64_t)probs) + i;
+    Problem x{};
+    x.subgrids = p->subgrids;
+    x.g_uv = p->g_uv;
+    x.g_w = p->g_w;
+    x.uvw = p->uvw;
+    x.vis = p->vis;
+    x.n_v = p->n_v;
+    x.n_u = p->n_u;
+    x.n_w = p->n_w;
+    x.log2_os_uv = p->log2_os_uv;
+    x.log2_os_w = p->log2_os_w;
+    x.guv_bytes = p->guv_bytes;
+    x.sub_bytes = p->sub_bytes;
+    x.hi_u = p->hi_u;
+    x.hi_v = p->hi_v;
+    x.hi_w = p->hi_w;
+    return x;
+}
+
+__device__ __forceinline__ const double* problem_uvw(const LaunchParams& P, int problem) {
+    if (!P.probs) return P.prob.uvw;
+    const ConstProblemPtr p = (ConstProblemPtr)uniform_u64((uint64_t)P.probs) + problem;
+    return p->uvw;
+}
+
+// G_w[o_w][0..3] as four floats, read through the scalar cache.
+template <int F>
+__device__ __forceinline__ float4 load_gw_row(uint64_t g_w, int ow) {
+    if constexpr (F == kGcfF32) {
+        const ConstF32Ptr p = (ConstF32Ptr)g_w + ow * kSupportW;
+        return make_float4(p[0], p[1], p[2], p[3]);
+    } else {
+        const ConstU32Ptr p = (ConstU32Ptr)g_w + ow * (kSupportW / 2);
+        const __half2 a = __builtin_bit_cast(__half2, p[0]);
+        const __half2 b = __builtin_bit_cast(__half2, p[1]);
+        return make_float4(__low2float(a), __high2float(a), __low2float(b), __high2float(b));
+    }
+}
+
+
+// Waits for this wavefront's outstanding vector-memory operations, including
+// loads that write LDS directly.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// LDS box of one wavefront: a copy of the cells of a tile's bounding box,
+// row-major. Complex64 cells are split into two planes of 16 bytes (w 0-1
+// and w 2-3), plane 1 starting plane1 bytes after plane 0, so that eight
+// lanes reading neighbouring cells touch one contiguous 128-byte span.
+template <int G>
+__device__ __forceinline__ void lds_w4(const char* box, uint32_t off, uint32_t plane1,
+                                       uint32_t (&raw)[GridTraits<G>::kWords]) {
+    const uint4 a = *reinterpret_cast<const uint4*>(box + off);
+    raw[0] = a.x; raw[1] = a.y; raw[2] = a.z; raw[3] = a.w;
+    if constexpr (G == kGridC64) {
+        const uint4 b = *reinterpret_cast<const uint4*>(box + plane1 + off);
+        raw[4] = b.x; raw[5] = b.y; raw[6] = b.z; raw[7] = b.w;
+    }
+}
+
+// Kernel variants: (LDS box per wavefront in bytes, largest tile). Box 0
+// gathers through the caches only.
+struct Variant { int box; int nb; };
+constexpr Variant kVariants[] = {{0, 64}, {8192, 32}, {12288, 32}, {16384, 32}, {16384, 64}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+}  // namespace
+}  // namespace dg

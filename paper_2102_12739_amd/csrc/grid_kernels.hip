@@ -1,0 +1,469 @@
+// gfx950 kernels for gridding, the adjoint of 3D degridding (the transpose
+// of the sum in Section 2): the tile kernel with an LDS staging box, the
+// owner-computes kernel over plan-time output blocks, and its fix-up pass.
+#include "dg_device.h"
+
+namespace dg {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Adjoint (gridding) kernel
+// ---------------------------------------------------------------------------
+//
+// The transpose of degridding: every in-range visibility V adds
+// G_w[o_w][t_w] * G_uv[o_v][o_u][t_v][t_u] * V to the cell (y + t_v, x + t_u,
+// z + t_w). Lanes map onto the 8 x 8 (t_v, t_u) taps as in the gather. When
+// the tile's cells fit the wavefront's LDS box, contributions are summed
+// there first (plain read-modify-write: a visibility's taps are distinct
+// cells and LDS operations of one wavefront run in order) and the box is added to the output once
+// with global float atomics; otherwise each contribution is a global atomic.
+
+// V times the four G_w taps of one visibility, interleaved (re, im).
+struct WeightedVis {
+    float c[8];
+};
+
+template <int F, int BOX, int NB>
+__global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParams P) {
+    static_assert(NB % 8 == 0 && NB <= kMaxNb, "tile size");
+    constexpr int kBoxBytes = BOX > 0 ? BOX : 16;
+    constexpr uint32_t kCell = kSupportW * 8;   // complex64 cell of 4 w values
+    __shared__ __attribute__((aligned(16))) char s_box[kWavesPerBlock][kBoxBytes];
+
+    const int lane = lane_id();
+    const int wv = (int)(threadIdx.x / kWave);
+    QueueState st{xcc_id() % P.q.n_queues, 0};
+    uint32_t wave_oob = 0;
+
+    int t = pop_tile(P.q, P.ctl, st);
+    while (t >= 0) {
+        const Tile tc = load_tile(P.tiles, t);
+        const int t_next = pop_tile(P.q, P.ctl, st);
+        const Problem pr = P.probs ? load_problem(P.probs, tc.problem) : P.prob;
+        const int count = tc.count;
+
+        // Coordinate stage; lane j also forms G_w * V of visibility j.
+        int32_t x0 = 0, y0 = 0, cell = 0, tab = 0, ow = 0;
+        bool in_range = false;
+        WeightedVis cw;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cw.c[q] = 0.0f;
+        if (lane < count) {
+            const int64_t i = P.tile_vis[(int64_t)t * kMaxNb + lane];
+            in_range = vis_coords(pr, i, cell, tab, ow, x0, y0);
+            if (in_range) {
+                const float2 vv = static_cast<const float2*>(pr.vis)[i];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float gw = load_gcf<F>(pr.g_w, ow * kSupportW + k);
+                    cw.c[2 * k] = gw * vv.x;
+                    cw.c[2 * k + 1] = gw * vv.y;
+                }
+            }
+        }
+        wave_oob += (uint32_t)__popcll(__ballot(lane < count && !in_range));
+
+        // G_uv weights of the whole tile (zero for out-of-range visibilities).
+        const __amdgpu_buffer_rsrc_t rg = make_rsrc(pr.g_uv, pr.guv_bytes);
+        const uint32_t lane_g = (uint32_t)lane * GcfTraits<F>::kBytes;
+        const int g_off = in_range ? tab * (int)GcfTraits<F>::kBytes : (int)kOutOfRange;
+        float gv[NB];
+#pragma unroll
+        for (int g0 = 0; g0 < NB; g0 += 8) {
+            if (g0 < count) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    gv[g0 + k] = load_gcf_rsrc<F>(rg, (uint32_t)__builtin_amdgcn_readlane(g_off, g0 + k) + lane_g);
+            }
+        }
+
+        bool staged = false;
+        int bx0 = 0, by0 = 0, bw = 0, bh = 0, bp = 0;
+        if constexpr (BOX > 0) {
+            bx0 = uniform(wave_min(in_range ? x0 : 0x7FFFFFFF));
+            by0 = uniform(wave_min(in_range ? y0 : 0x7FFFFFFF));
+            const int bx1 = uniform(wave_max(in_range ? x0 : -1));
+            const int by1 = uniform(wave_max(in_range ? y0 : -1));
+            if (bx1 >= 0) {
+                bw = bx1 - bx0 + kSupportUV;
+                bh = by1 - by0 + kSupportUV;
+                bp = bw + ((8 - bw) & 15);
+                staged = (uint32_t)(bp * bh) * kCell <= (uint32_t)BOX;
+            }
+        }
+
+        float* out = static_cast<float*>(pr.grid_out) + 2 * (int64_t)tc.sub * pr.n_v * pr.n_u * pr.n_w;
+        const int tv = lane >> 3, tu = lane & 7;
+        if (staged) {
+            char* box = s_box[wv];
+            const int n_chunks = bp * bh * (int)(kCell / 16);
+            for (int c = lane; c < n_chunks; c += kWave)
+                *reinterpret_cast<uint4*>(box + (uint32_t)c * 16u) = make_uint4(0u, 0u, 0u, 0u);
+            wave_lds_sync();
+            const int rel = in_range ? ((y0 - by0) * bp + (x0 - bx0)) : 0;
+            const uint32_t lane_box = ((uint32_t)tv * bp + tu) * kCell;
+#pragma unroll
+            for (int g0 = 0; g0 < NB; g0 += 8) {
+                if (g0 < count) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int j = g0 + k;
+                        const uint32_t base = lane_box + (uint32_t)__builtin_amdgcn_readlane(rel, j) * kCell;
+                        // distinct cells per visibility, in-order LDS: plain
+                        // read-modify-write is exact
+                        float4* dst = reinterpret_cast<float4*>(box + base);
+                        float c[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            c[q] = gv[j] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cw.c[q]), j));
+                        float4 a = dst[0], b = dst[1];
+                        a.x += c[0]; a.y += c[1]; a.z += c[2]; a.w += c[3];
+                        b.x += c[4]; b.y += c[5]; b.z += c[6]; b.w += c[7];
+                        dst[0] = a;
+                        dst[1] = b;
+                    }
+                }
+            }
+            wave_lds_sync();
+            // Add the box to the output row by row: a box row is bw * 8
+            // consecutive floats both in LDS and in the subgrid, so lane l of
+            // a step adds float l and one atomic instruction covers 256
+            // contiguous bytes.
+            const int row_floats = bw * (int)(kCell / 4);
+            const float* lds_rows = reinterpret_cast<const float*>(box);
+            for (int row = 0; row < bh; ++row) {
+                float* dst = out + 2 * ((int64_t)((by0 + row) * pr.n_u + bx0) * pr.n_w);
+                const float* src = lds_rows + (uint32_t)row * bp * (kCell / 4);
+                for (int f = lane; f < row_floats; f += kWave) {
+                    const float v = src[f];
+                    if (v != 0.0f) unsafeAtomicAdd(dst + f, v);
+                }
+            }
+            wave_lds_sync();
+        } else {
+            const int64_t lane_cell = (int64_t)(tv * pr.n_u + tu) * pr.n_w;
+#pragma unroll
+            for (int g0 = 0; g0 < NB; g0 += 8) {
+                if (g0 < count) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int j = g0 + k;
+                        const int cj = __builtin_amdgcn_readlane(in_range ? cell : -1, j);
+                        if (cj >= 0) {
+                            float* dst = out + 2 * ((int64_t)cj + lane_cell);
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cw.c[q]), j));
+                                unsafeAtomicAdd(dst + q, gv[j] * c);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        t = t_next;
+    }
+    finish_launch(P.ctl, wave_oob);
+}
+
+// ---------------------------------------------------------------------------
+// Owner-computes adjoint
+// ---------------------------------------------------------------------------
+//
+// A wavefront owns one output block of kOwnerBlock x kOwnerBlock cells of
+// one subgrid. It walks the block's visibility list (made at plan time from
+// the sorted coordinates), adds each visibility's taps that fall inside the
+// block to an LDS copy of the block, and writes the block once with plain
+// stores: no global atomics, and the sums do not depend on timing. A listed
+// visibility whose first tap at run time differs from the plan's is skipped
+// here; the fix-up pass adds those with atomics.
+
+struct OwnerRec {
+    int32_t x0, y0;   // first tap relative to the block origin (x0 far out of range: skipped)
+    int32_t g_off;    // byte offset of the G_uv block (kOutOfRange if skipped)
+    int32_t pad;
+    float c[8];       // G_w[o_w][t] * V, interleaved (re, im) for t = 0..3
+};
+static_assert(sizeof(OwnerRec) == 48, "OwnerRec layout");
+
+typedef const __attribute__((address_space(4))) OwnerBlock* ConstOwnerBlockPtr;
+
+// This lane's G_uv weights of records j0 .. j0+7 (zero for skipped records).
+template <int F>
+__device__ __forceinline__ void load_weights8(float* g, const OwnerRec* rec, int j0, __amdgpu_buffer_rsrc_t rg,
+                                              uint32_t lane_g) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g[k] = load_gcf_rsrc<F>(rg, (uint32_t)uniform(rec[j0 + k].g_off) + lane_g);
+}
+
+// Marks eight values as used here, so that their loads stay where they were
+// issued (one group ahead) instead of being moved next to each use.
+__device__ __forceinline__ void pin8(float* g) {
+    asm volatile("" ::"v"(g[0]), "v"(g[1]), "v"(g[2]), "v"(g[3]), "v"(g[4]), "v"(g[5]), "v"(g[6]), "v"(g[7]));
+}
+
+template <int F>
+__global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P) {
+    constexpr int B = kOwnerBlock;
+    constexpr int kCellFloats = kSupportW * 2;          // complex64 x 4 w
+    constexpr int kRowFloats = B * kCellFloats;         // floats of one block row
+    // LDS row pitch: 16 bytes more than a row (cells stay 16-byte aligned and
+    // neighbouring rows start on different banks)
+    constexpr int kPitch = kRowFloats + 4;
+    __shared__ __attribute__((aligned(16))) float s_box[kWavesPerBlock][B * kPitch];
+    __shared__ OwnerRec s_rec[kWavesPerBlock][kWave];
+
+    const int lane = lane_id();
+    const int wv = (int)(threadIdx.x / kWave);
+    const int tv = lane >> 3, tu = lane & 7;
+    QueueState st{xcc_id() % P.q.n_queues, 0};
+    const Problem& pr = P.prob;
+    const __amdgpu_buffer_rsrc_t rg = make_rsrc(pr.g_uv, pr.guv_bytes);
+    const uint32_t lane_g = (uint32_t)lane * GcfTraits<F>::kBytes;
+    const int64_t row_floats = 2 * (int64_t)pr.n_u * pr.n_w;   // floats per subgrid row
+    float* box = s_box[wv];
+
+    int t = pop_tile(P.q, P.ctl, st);
+    while (t >= 0) {
+        const ConstOwnerBlockPtr pb = (ConstOwnerBlockPtr)uniform_u64((uint64_t)P.blocks) + t;
+        const int64_t begin = pb->begin;
+        const int count = pb->count;
+        const int blk = pb->block;
+        const int t_next = pop_tile(P.q, P.ctl, st);
+        const int per_sub = P.nby * P.nbx;
+        const int s = blk / per_sub;
+        const int by = (blk - s * per_sub) / P.nbx;
+        const int bx = blk - s * per_sub - by * P.nbx;
+        float* out = static_cast<float*>(pr.grid_out) +
+                     2 * ((int64_t)s * pr.cells_per_sub + ((int64_t)(by * B) * pr.n_u + bx * B) * pr.n_w);
+
+        // the block's current contents (or zeros): one float per lane and step
+#pragma unroll 4
+        for (int f = lane; f < B * kRowFloats; f += kWave) {
+            const int row = f / kRowFloats, col = f - row * kRowFloats;
+            box[row * kPitch + col] = P.accumulate ? out[row * row_floats + col] : 0.0f;
+        }
+
+        for (int c0 = 0; c0 < count; c0 += kWave) {
+            OwnerRec r;
+            r.x0 = -(1 << 20);
+            r.y0 = 0;
+            r.g_off = (int)kOutOfRange;
+            r.pad = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r.c[q] = 0.0f;
+            if (c0 + lane < count) {
+                const int64_t i = P.items[begin + c0 + lane];
+                const double* uv = pr.uvw + 3 * i;
+                int32_t cell = 0, tab = 0, ow = 0, x0 = 0, y0 = 0;
+                if (coords_from(pr, uv[0], uv[1], uv[2], cell, tab, ow, x0, y0) &&
+                    (((uint32_t)y0 << 16) | (uint32_t)x0) == P.plan_start[i]) {
+                    r.x0 = x0 - bx * B;
+                    r.y0 = y0 - by * B;
+                    r.g_off = tab * (int)GcfTraits<F>::kBytes;
+                    const float2 vv = static_cast<const float2*>(pr.vis)[i];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float gw = load_gcf<F>(pr.g_w, ow * kSupportW + k);
+                        r.c[2 * k] = gw * vv.x;
+                        r.c[2 * k + 1] = gw * vv.y;
+                    }
+                }
+            }
+            s_rec[wv][lane] = r;
+            wave_lds_sync();
+            const int n = min(kWave, count - c0);
+            // G_uv weights one group of eight ahead (records past n are
+            // skipped ones, whose loads return zero)
+            float g[2][8];
+            load_weights8<F>(g[0], s_rec[wv], 0, rg, lane_g);
+#pragma unroll
+            for (int j0 = 0; j0 < kWave; j0 += 8) {
+                if (j0 < n) {
+                    float* gc = g[(j0 / 8) & 1];
+                    if (j0 + 8 < kWave) load_weights8<F>(g[((j0 / 8) + 1) & 1], s_rec[wv], j0 + 8, rg, lane_g);
+                    pin8(gc);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const OwnerRec& rj = s_rec[wv][j0 + k];
+                        const int cy = rj.y0 + tv, cx = rj.x0 + tu;
+                        if ((unsigned)cy < (unsigned)B && (unsigned)cx < (unsigned)B) {
+                            // the taps of one visibility are distinct cells and
+                            // LDS operations of a wavefront run in order, so a
+                            // plain read-modify-write is exact
+                            float4* dst = reinterpret_cast<float4*>(box + cy * kPitch + cx * kCellFloats);
+                            float4 a = dst[0], b = dst[1];
+                            a.x += gc[k] * rj.c[0]; a.y += gc[k] * rj.c[1];
+                            a.z += gc[k] * rj.c[2]; a.w += gc[k] * rj.c[3];
+                            b.x += gc[k] * rj.c[4]; b.y += gc[k] * rj.c[5];
+                            b.z += gc[k] * rj.c[6]; b.w += gc[k] * rj.c[7];
+                            dst[0] = a;
+                            dst[1] = b;
+                        }
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+
+        // write the block
+#pragma unroll 4
+        for (int f = lane; f < B * kRowFloats; f += kWave) {
+            const int row = f / kRowFloats, col = f - row * kRowFloats;
+            out[row * row_floats + col] = box[row * kPitch + col];
+        }
+        wave_lds_sync();
+        t = t_next;
+    }
+    finish_launch(P.ctl, 0u);
+}
+
+// Visibilities the owner pass skipped (first tap differs from the plan's),
+// added with atomics by whole wavefronts, and the out-of-range count.
+template <int F>
+__global__ __launch_bounds__(kBlockThreads) void grid_fixup_kernel(Problem pr, const int64_t* offsets,
+                                                                   int64_t n_sub, int64_t n_vis,
+                                                                   const uint32_t* plan_start, Ctl* ctl) {
+    const int lane = lane_id();
+    const int tv = lane >> 3, tu = lane & 7;
+    uint32_t wave_oob = 0;
+    const int64_t n_waves = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t first = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    for (int64_t w0 = first * kWave; w0 < n_vis; w0 += n_waves * kWave) {
+        const int64_t i = w0 + lane;
+        int32_t cell = 0, tab = 0, ow = 0, x0 = 0, y0 = 0;
+        bool in_range = false, redo = false;
+        if (i < n_vis) {
+            const double* uv = pr.uvw + 3 * i;
+            in_range = coords_from(pr, uv[0], uv[1], uv[2], cell, tab, ow, x0, y0);
+            redo = in_range && (((uint32_t)y0 << 16) | (uint32_t)x0) != plan_start[i];
+        }
+        wave_oob += (uint32_t)__popcll(__ballot(i < n_vis && !in_range));
+        uint64_t mask = __ballot(redo);
+        if (mask == 0) continue;
+        // subgrid of each visibility to redo
+        int64_t sub = 0;
+        if (redo) {
+            int64_t lo = 0, hi = n_sub;
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (offsets[mid] <= i) lo = mid; else hi = mid;
+            }
+            sub = lo;
+        }
+        float c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = 0.0f;
+        if (redo) {
+            const float2 vv = static_cast<const float2*>(pr.vis)[i];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float gw = load_gcf<F>(pr.g_w, ow * kSupportW + k);
+                c[2 * k] = gw * vv.x;
+                c[2 * k + 1] = gw * vv.y;
+            }
+        }
+        const int64_t lane_cell = (int64_t)(tv * pr.n_u + tu) * pr.n_w;
+        while (mask) {
+            const int j = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const int64_t sj = ((int64_t)__builtin_amdgcn_readlane((int)(sub >> 32), j) << 32) |
+                               (uint32_t)__builtin_amdgcn_readlane((int)sub, j);
+            const int cj = __builtin_amdgcn_readlane(cell, j);
+            const int tj = __builtin_amdgcn_readlane(tab, j);
+            const float g = load_gcf<F>(pr.g_uv, (int64_t)tj + lane);
+            float* dst = static_cast<float*>(pr.grid_out) + 2 * (sj * pr.cells_per_sub + cj + lane_cell);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                unsafeAtomicAdd(dst + q, g * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c[q]), j)));
+        }
+    }
+    finish_launch(ctl, wave_oob);
+}
+
+}  // namespace
+
+int adjoint_variant_count() { return kNumVariants; }
+
+template <int F, int V>
+hipError_t launch_adjoint_t(const LaunchParams& p, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((grid_adjoint_kernel<F, kVariants[V].box, kVariants[V].nb>), dim3(blocks), dim3(kBlockThreads),
+                       0, s, p);
+    return hipGetLastError();
+}
+
+template <int F, int V>
+hipError_t occ_adjoint_t(int* n) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        n, grid_adjoint_kernel<F, kVariants[V].box, kVariants[V].nb>, kBlockThreads, 0);
+}
+
+template <int F>
+hipError_t launch_adjoint_v(const LaunchParams& p, int variant, int blocks, hipStream_t s) {
+    switch (variant) {
+        case 0: return launch_adjoint_t<F, 0>(p, blocks, s);
+        case 1: return launch_adjoint_t<F, 1>(p, blocks, s);
+        case 2: return launch_adjoint_t<F, 2>(p, blocks, s);
+        case 3: return launch_adjoint_t<F, 3>(p, blocks, s);
+        case 4: return launch_adjoint_t<F, 4>(p, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int F>
+hipError_t occ_adjoint_v(int variant, int* n) {
+    switch (variant) {
+        case 0: return occ_adjoint_t<F, 0>(n);
+        case 1: return occ_adjoint_t<F, 1>(n);
+        case 2: return occ_adjoint_t<F, 2>(n);
+        case 3: return occ_adjoint_t<F, 3>(n);
+        case 4: return occ_adjoint_t<F, 4>(n);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant, int blocks,
+                               hipStream_t stream) {
+    if (gcf_kind == kGcfF32) return launch_adjoint_v<kGcfF32>(p, variant, blocks, stream);
+    if (gcf_kind == kGcfF16) return launch_adjoint_v<kGcfF16>(p, variant, blocks, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t adjoint_kernel_occupancy(int gcf_kind, int variant, int* n) {
+    if (gcf_kind == kGcfF32) return occ_adjoint_v<kGcfF32>(variant, n);
+    if (gcf_kind == kGcfF16) return occ_adjoint_v<kGcfF16>(variant, n);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_grid_owner(const OwnerParams& p, int gcf_kind, int blocks, hipStream_t stream) {
+    if (gcf_kind == kGcfF32)
+        hipLaunchKernelGGL((grid_owner_kernel<kGcfF32>), dim3(blocks), dim3(kBlockThreads), 0, stream, p);
+    else if (gcf_kind == kGcfF16)
+        hipLaunchKernelGGL((grid_owner_kernel<kGcfF16>), dim3(blocks), dim3(kBlockThreads), 0, stream, p);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t owner_kernel_occupancy(int gcf_kind, int* n) {
+    if (gcf_kind == kGcfF32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, grid_owner_kernel<kGcfF32>, kBlockThreads, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, grid_owner_kernel<kGcfF16>, kBlockThreads, 0);
+}
+
+hipError_t launch_grid_fixup(const Problem& pr, const int64_t* vis_offsets, int64_t n_sub, int64_t n_vis,
+                             const uint32_t* plan_start, Ctl* ctl, int gcf_kind, hipStream_t stream) {
+    int64_t blocks = (n_vis + kBlockThreads - 1) / kBlockThreads;
+    blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+    if (gcf_kind == kGcfF32)
+        hipLaunchKernelGGL((grid_fixup_kernel<kGcfF32>), dim3((unsigned)blocks), dim3(kBlockThreads), 0, stream, pr,
+                           vis_offsets, n_sub, n_vis, plan_start, ctl);
+    else if (gcf_kind == kGcfF16)
+        hipLaunchKernelGGL((grid_fixup_kernel<kGcfF16>), dim3((unsigned)blocks), dim3(kBlockThreads), 0, stream, pr,
+                           vis_offsets, n_sub, n_vis, plan_start, ctl);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace dg
