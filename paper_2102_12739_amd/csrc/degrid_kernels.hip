@@ -41,14 +41,14 @@ struct Fetch8 {
 // Lane j holds the coordinate-stage results of visibility j: a_off (byte
 // offset of its first tap in the LDS box or in the subgrid) and ow (its G_w
 // row); v_readlane hands them to the whole wavefront.
-template <int G, bool STAGED>
+template <int G, bool STAGED, uint32_t PLANE1>
 __device__ __forceinline__ void fetch8(Fetch8<G>& f, int g0, int a_off, __amdgpu_buffer_rsrc_t ra,
-                                       uint32_t lane_a, const char* box, uint32_t plane1) {
+                                       uint32_t lane_a, const char* box) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const uint32_t aj = (uint32_t)__builtin_amdgcn_readlane(a_off, g0 + k);
         if constexpr (STAGED) {
-            lds_w4<G>(box, lane_a + aj, plane1, f.raw[k]);
+            lds_w4<G, PLANE1>(box, lane_a + aj, f.raw[k]);
         } else {
             load_w4<G>(ra, lane_a + aj, f.raw[k]);
         }
@@ -79,17 +79,17 @@ __device__ __forceinline__ void sum8(const Fetch8<G>& f, const float* gv, int ow
 }
 
 // All visibilities of a tile, groups of eight in a two-stage pipeline.
-template <int G, int F, int NB, bool STAGED>
+template <int G, int F, int NB, bool STAGED, uint32_t PLANE1>
 __device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, int ow, const float* gv,
                                             __amdgpu_buffer_rsrc_t ra, uint64_t g_w, uint32_t lane_a,
-                                            const char* box, uint32_t plane1) {
+                                            const char* box) {
     Fetch8<G> buf[2];
-    fetch8<G, STAGED>(buf[0], 0, a_off, ra, lane_a, box, plane1);
+    fetch8<G, STAGED, PLANE1>(buf[0], 0, a_off, ra, lane_a, box);
 #pragma unroll
     for (int g0 = 0; g0 < NB; g0 += 8) {
         if (g0 < count) {
             if (g0 + 8 < NB && g0 + 8 < count)
-                fetch8<G, STAGED>(buf[((g0 / 8) + 1) & 1], g0 + 8, a_off, ra, lane_a, box, plane1);
+                fetch8<G, STAGED, PLANE1>(buf[((g0 / 8) + 1) & 1], g0 + 8, a_off, ra, lane_a, box);
             sum8<G, F>(buf[(g0 / 8) & 1], gv + g0, ow, g_w, out, g0);
         }
     }
@@ -108,6 +108,7 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
     using GT = GridTraits<G>;
     static_assert(NB % 8 == 0 && NB <= kMaxNb, "tile size");
     constexpr int kBoxBytes = BOX > 0 ? BOX : 16;
+    constexpr uint32_t kPlane1 = kBoxBytes / 2;   // complex64: w 2-3 of every slot
     __shared__ float2 s_out[kWavesPerBlock][NB];
     __shared__ __attribute__((aligned(16))) char s_box[kWavesPerBlock][kBoxBytes];
 
@@ -132,6 +133,9 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
         }
     }
     int t_nxt = t >= 0 ? pop_tile(P.q, P.ctl, st) : -1;
+    // pop of the tile after t_nxt, sent during the previous tile
+    bool pend = false;
+    uint32_t raw = 0;
 
     while (t >= 0) {
         const Problem pr = P.probs ? load_problem(P.probs, tc.problem) : P.prob;
@@ -152,7 +156,11 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
             tn = load_tile(P.tiles, t_nxt);
             vis_n = P.tile_vis[(int64_t)t_nxt * kMaxNb + lane];
         }
-        const int t_after = has_next ? pop_tile(P.q, P.ctl, st) : -1;
+        // (wave-uniform: both pops return a readfirstlane value; stated so
+        // that the tile descriptors derived from it stay in scalar registers)
+        const int t_after =
+            uniform(!has_next ? -1 : (pend ? pop_resolve(P.q, P.ctl, st, raw) : pop_tile(P.q, P.ctl, st)));
+        pend = false;
 
         const char* sub_base = static_cast<const char*>(pr.subgrids) + (int64_t)tc.sub * pr.sub_bytes;
         const __amdgpu_buffer_rsrc_t ra = make_rsrc(sub_base, pr.sub_bytes);
@@ -194,30 +202,40 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
         char* box = s_box[wv];
         if (staged) {
             // Copy the box with loads that write LDS directly (lane l of a step
-            // fills 16 bytes at 16 * l), all in flight at once. LDS chunk c is
-            // half c / n_slots of slot c mod n_slots (complex64), or slot c;
-            // slot (row, col) with col >= bw is row padding (filled with zeros).
-            constexpr int kHalves = (int)(kCellBytes<G> / 16);   // 2 for complex64, else 1
+            // fills 16 bytes at 16 * l), all in flight at once. Slot s = row *
+            // bp + col holds the cell's first 16 bytes (complex64: w 0-1; else
+            // the whole cell) at 16 * s, and complex64's w 2-3 at kPlane1 +
+            // 16 * s; columns col >= bw are row padding (filled with zeros).
             const int n_slots = bp * bh;
-            const int total = n_slots * kHalves;
-            const float inv_bp = 1.0f / (float)bp;
             const uint32_t row_stride = (uint32_t)pr.n_u * pr.n_w * GT::kElemBytes;
             const uint32_t box_origin = ((uint32_t)by0 * pr.n_u + bx0) * pr.n_w * GT::kElemBytes;
-            for (int c0 = 0; c0 < total; c0 += kWave) {
-                const int c = c0 + lane;
-                const int half = (kHalves == 2 && c >= n_slots) ? 1 : 0;
-                const int cc = c - half * n_slots;
-                const int row = (int)(((float)cc + 0.5f) * inv_bp);
-                const int col = cc - row * bp;
-                const uint32_t off = (c < total && col < bw)
-                                         ? box_origin + (uint32_t)row * row_stride + (uint32_t)col * kCellBytes<G> +
-                                               (uint32_t)half * 16u
+            const int drow = kWave / bp, dcol = kWave - drow * bp;
+            int row = lane / bp;
+            int col = lane - row * bp;
+            for (int s0 = 0; s0 < n_slots; s0 += kWave) {
+                const uint32_t off = (s0 + lane < n_slots && col < bw)
+                                         ? box_origin + (uint32_t)row * row_stride + (uint32_t)col * kCellBytes<G>
                                          : kOutOfRange;
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                    ra, (__attribute__((address_space(3))) void*)(box + c0 * 16), 16, off, 0, 0, 0);
+                    ra, (__attribute__((address_space(3))) void*)(box + s0 * 16), 16, off, 0, 0, 0);
+                if constexpr (G == kGridC64)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        ra, (__attribute__((address_space(3))) void*)(box + kPlane1 + s0 * 16), 16, off + 16u, 0, 0,
+                        0);
+                row += drow;
+                col += dcol;
+                if (col >= bp) {
+                    col -= bp;
+                    ++row;
+                }
             }
             wait_vmem();
             wave_lds_sync();
+            // the pop of the tile after next travels while this tile is gathered
+            if (t_after >= 0) {
+                raw = pop_issue(P.ctl, st);
+                pend = true;
+            }
         }
 
         // Next tile's coordinates: requested now when the gather below reads
@@ -230,15 +248,19 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
             wn = uvw_n[3 * vis_n + 2];
         }
 
-        const uint32_t plane1 = (uint32_t)(bp * bh) * 16u;
         const int a_off = staged ? (in_range ? ((y0 - by0) * bp + (x0 - bx0)) * 16 : 0)
                                  : (in_range ? cell * (int)GT::kElemBytes : (int)kOutOfRange);
         const uint32_t lane_a = staged ? ((uint32_t)(lane >> 3) * bp + (lane & 7)) * 16u
                                        : (uint32_t)(((lane >> 3) * pr.n_u + (lane & 7)) * pr.n_w) * GT::kElemBytes;
-        if (staged)
-            gather_tile<G, F, NB, true>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box, plane1);
-        else
-            gather_tile<G, F, NB, false>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box, plane1);
+        if (staged) {
+            gather_tile<G, F, NB, true, kPlane1>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
+        } else {
+            gather_tile<G, F, NB, false, kPlane1>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
+            if (t_after >= 0) {
+                raw = pop_issue(P.ctl, st);
+                pend = true;
+            }
+        }
         if (!staged && has_next && lane < tn.count) {
             un = uvw_n[3 * vis_n];
             vn = uvw_n[3 * vis_n + 1];

@@ -73,6 +73,24 @@ __device__ __forceinline__ int pop_tile(const QueueSpec& qs, Ctl* ctl, QueueStat
     return -1;
 }
 
+// The two halves of a pop whose atomic is left in flight while the
+// wavefront works: pop_issue sends the cursor increment of the current queue
+// and returns without waiting; pop_resolve (called later) turns the returned
+// index into a tile, or, when that queue has run dry, carries on as pop_tile.
+__device__ __forceinline__ uint32_t pop_issue(Ctl* ctl, const QueueState& st) {
+    uint32_t idx = 0;
+    if (lane_id() == 0) idx = atomicAdd(&ctl->cursor[st.q].v[0], 1u);
+    return idx;
+}
+
+__device__ __forceinline__ int pop_resolve(const QueueSpec& qs, Ctl* ctl, QueueState& st, uint32_t idx) {
+    const int t = qs.begin[st.q] + uniform((int)idx);
+    if (t < qs.end[st.q]) return t;
+    st.q = (st.q + 1 == qs.n_queues) ? 0 : st.q + 1;
+    st.tried++;
+    return pop_tile(qs, ctl, st);
+}
+
 // Adds this wavefront's out-of-range count; the last workgroup of the launch
 // publishes the launch total and resets cursors and counters for the next.
 __device__ __forceinline__ void finish_launch(Ctl* ctl, uint32_t wave_oob) {
@@ -345,15 +363,15 @@ __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70)
 
 // LDS box of one wavefront: a copy of the cells of a tile's bounding box,
 // row-major. Complex64 cells are split into two planes of 16 bytes (w 0-1
-// and w 2-3), plane 1 starting plane1 bytes after plane 0, so that eight
+// and w 2-3), plane 1 starting PLANE1 bytes after plane 0 (half the box, a
+// constant, so it becomes the LDS instruction's offset field), so that eight
 // lanes reading neighbouring cells touch one contiguous 128-byte span.
-template <int G>
-__device__ __forceinline__ void lds_w4(const char* box, uint32_t off, uint32_t plane1,
-                                       uint32_t (&raw)[GridTraits<G>::kWords]) {
+template <int G, uint32_t PLANE1>
+__device__ __forceinline__ void lds_w4(const char* box, uint32_t off, uint32_t (&raw)[GridTraits<G>::kWords]) {
     const uint4 a = *reinterpret_cast<const uint4*>(box + off);
     raw[0] = a.x; raw[1] = a.y; raw[2] = a.z; raw[3] = a.w;
     if constexpr (G == kGridC64) {
-        const uint4 b = *reinterpret_cast<const uint4*>(box + plane1 + off);
+        const uint4 b = *reinterpret_cast<const uint4*>(box + off + PLANE1);
         raw[4] = b.x; raw[5] = b.y; raw[6] = b.z; raw[7] = b.w;
     }
 }
