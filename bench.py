@@ -197,8 +197,13 @@ def main(argv=None):
                     help="time the plan without the plan-time work order (degrid_plan_sort)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-patterns", action="store_true",
-                    help="skip the batched and differentiation measurements")
+                    help="skip the latency, batched and differentiation measurements")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the timed steps of the sorted plan (for a profiler's per-kernel statistics): "
+                         "no input-order run, per-launch distributions, storage variants, CPU baseline or patterns")
     args = ap.parse_args(argv)
+    if args.main_only:
+        args.no_cpu_baseline = args.no_variants = args.no_patterns = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the degridding path shards by subgrid with no exchange; see the design notes)",
@@ -219,8 +224,9 @@ def main(argv=None):
     inputs = upload_inputs(p)
     out = torch.empty(p.n_vis, dtype=torch.complex64, device="cuda:0")
     plan = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w)
-    # the input-order figure is always measured (and reported beside the main one)
-    ms_in_order, kms_in_order = time_plan(plan, inputs, out, args.steps, args.warmup)
+    # the input-order figure is measured too (and reported beside the main one)
+    if not args.main_only:
+        ms_in_order, kms_in_order = time_plan(plan, inputs, out, args.steps, args.warmup)
     sort_s = None
     if not args.input_order:
         t = time.perf_counter()
@@ -265,32 +271,34 @@ def main(argv=None):
     # Per-launch distribution, back to back (warm) and after writing 1 GiB
     # between launches (cold L2 and Infinity Cache), plus what the memory
     # system does on a plain copy and the bytes a launch cannot avoid.
-    flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda:0")
-    run = lambda: plan.execute(*inputs, out=out)   # noqa: E731
-    warm = percentiles(launch_times(run, 50))
-    cold = percentiles(launch_times(run, 20, flush=lambda: flush_buf.fill_(1.0)))
-    del flush_buf
-    torch.cuda.empty_cache()
-    comp = compulsory_bytes(p, 8)
-    result["timing"] = {
-        "warm_kernel_ms": warm, "cold_kernel_ms": cold,
-        "warm_median_value": p.n_vis / (warm["median"] * 1e-3),
-        "cold_median_value": p.n_vis / (cold["median"] * 1e-3),
-        "cold_median_roofline_frac": bytes_launch / (cold["median"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-    }
-    result["roofline"]["copy_gbs"] = copy_bandwidth()
-    result["roofline"]["compulsory_bytes_per_launch"] = comp
-    result["roofline"]["compulsory_gbs_cold"] = comp / (cold["median"] * 1e-3) / 1e9
-    result["device"] = {"name": torch.cuda.get_device_name(0),
-                        "compute_units": torch.cuda.get_device_properties(0).multi_processor_count}
-    log(f"warm median {warm['median']:.4f} ms, cold median {cold['median']:.4f} ms, "
-        f"copy {result['roofline']['copy_gbs']:.0f} GB/s, compulsory {comp / 1e9:.3f} GB/launch")
+    if not args.main_only:
+        flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda:0")
+        run = lambda: plan.execute(*inputs, out=out)   # noqa: E731
+        warm = percentiles(launch_times(run, 50))
+        cold = percentiles(launch_times(run, 20, flush=lambda: flush_buf.fill_(1.0)))
+        del flush_buf
+        torch.cuda.empty_cache()
+        comp = compulsory_bytes(p, 8)
+        result["timing"] = {
+            "warm_kernel_ms": warm, "cold_kernel_ms": cold,
+            "warm_median_value": p.n_vis / (warm["median"] * 1e-3),
+            "cold_median_value": p.n_vis / (cold["median"] * 1e-3),
+            "cold_median_roofline_frac": bytes_launch / (cold["median"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        }
+        result["roofline"]["copy_gbs"] = copy_bandwidth()
+        result["roofline"]["compulsory_bytes_per_launch"] = comp
+        result["roofline"]["compulsory_gbs_cold"] = comp / (cold["median"] * 1e-3) / 1e9
+        result["device"] = {"name": torch.cuda.get_device_name(0),
+                            "compute_units": torch.cuda.get_device_properties(0).multi_processor_count}
+        log(f"warm median {warm['median']:.4f} ms, cold median {cold['median']:.4f} ms, "
+            f"copy {result['roofline']['copy_gbs']:.0f} GB/s, compulsory {comp / 1e9:.3f} GB/launch")
     if tune_s is not None:
         result["config"]["tune_s"] = tune_s
     result["config"]["work_order"] = ("input order" if args.input_order else
                                       "plan-time Z-order of cells (degrid_plan_sort, once per coordinate set)")
     if sort_s is not None:
         result["config"]["plan_sort_s"] = sort_s
+    if sort_s is not None and not args.main_only:
         result["input_order"] = {"value": p.n_vis / (ms_in_order * 1e-3), "ms_per_step": ms_in_order,
                                  "kernel_ms": kms_in_order,
                                  "achieved_gbs": bytes_launch / (kms_in_order * 1e-3) / 1e9}
@@ -369,7 +377,7 @@ def bench_batched(steps, warmup, check):
     import numpy as np
     import torch
     from paper_2102_12739_amd import workload as wl
-    from paper_2102_12739_amd.degrid import Batch, Plan
+    from paper_2102_12739_amd.degrid import Batch, Plan, batch_tune
     t = time.perf_counter()
     probs = wl.batched(seed=2)
     log(f"batched workload: {[p.n_subgrids for p in probs]} subgrids, {sum(p.n_vis for p in probs)} visibilities, "
@@ -383,8 +391,11 @@ def bench_batched(steps, warmup, check):
         pl.sort(i[3])
         plans.append(pl)
     plan_s = time.perf_counter() - t
-    batch = Batch(plans)
     args = [i for i in ins]
+    t = time.perf_counter()
+    kernel, n_b = batch_tune(plans, args, outs=outs)
+    tune_s = time.perf_counter() - t
+    batch = Batch(plans)
     stream = torch.cuda.current_stream()
     n_vis = sum(p.n_vis for p in probs)
 
@@ -396,7 +407,9 @@ def bench_batched(steps, warmup, check):
             pl.execute(*i, out=o, stream=stream)
 
     res = {"workload": "batched-8-problems-S4..64-loguniform-2^8..2^18-os8/16/32", "visibilities": n_vis,
-           "problems": len(probs), "plan_and_sort_s": plan_s}
+           "problems": len(probs), "plan_and_sort_s": plan_s,
+           "autotune": {"kernel": kernel, "n_b": n_b, "tune_s": tune_s,
+                        "candidates": "kernel variants x n_b in {8,16,32,64}, one batch launch each"}}
     for name, fn in (("batch_graph", run_batch), ("separate_launches", run_plain)):
         for _ in range(warmup):
             fn()
@@ -408,19 +421,68 @@ def bench_batched(steps, warmup, check):
         ms = (time.perf_counter() - t0) * 1e3 / steps
         res[name] = {"ms_per_step": ms, "value": n_vis / (ms * 1e-3)}
     res["speedup_batch_vs_separate"] = res["separate_launches"]["ms_per_step"] / res["batch_graph"]["ms_per_step"]
+    run_batch()
+    torch.cuda.synchronize()
+    fp32_out = [o.cpu().numpy().astype(np.complex128) for o in outs]
+    batch.close()
+    del ins, batch, plans
+    torch.cuda.empty_cache()
+
+    # The same eight problems with complex bf16 subgrids and fp16 tables
+    # (fp32 accumulation, fp64 index arithmetic), one graph launch.
+    bins = [upload_inputs(p, "cbf16", "f16") for p in probs]
+    bplans = []
+    for p, i in zip(probs, bins):
+        pl = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w, grid_dtype="cbf16", gcf_dtype="f16")
+        pl.sort(i[3])
+        bplans.append(pl)
+    t = time.perf_counter()
+    bkernel, bn_b = batch_tune(bplans, bins, outs=outs)
+    btune_s = time.perf_counter() - t
+    bbatch = Batch(bplans)
+
+    def run_bf16():
+        bbatch.execute(bins, outs=outs, stream=stream)
+
+    for _ in range(warmup):
+        run_bf16()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_bf16()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    res["batch_graph_bf16"] = {"ms_per_step": ms, "value": n_vis / (ms * 1e-3),
+                               "grid_dtype": "cbf16", "gcf_dtype": "f16",
+                               "autotune": {"kernel": bkernel, "n_b": bn_b, "tune_s": btune_s},
+                               "speedup_vs_plain_fp32_separate": res["separate_launches"]["ms_per_step"] / ms,
+                               "speedup_vs_batch_fp32": res["batch_graph"]["ms_per_step"] / ms,
+                               "achieved_gbs": BYTES_PER_VIS["cbf16"] * n_vis / (ms * 1e-3) / 1e9}
+    run_bf16()
+    torch.cuda.synchronize()
+    bf16_out = [o.cpu().numpy().astype(np.complex128) for o in outs]
+    bbatch.close()
     if check:
         import oracle
-        run_batch()
-        torch.cuda.synchronize()
-        num = den = 0.0
-        for p, o in zip(probs, outs):
+        acc = {"fp32": [0.0, 0.0], "bf16_vs_fp32_inputs": [0.0, 0.0], "bf16_vs_stored_inputs": [0.0, 0.0]}
+        worst = 0.0
+        for p, g32, g16 in zip(probs, fp32_out, bf16_out):
             ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
-            got = o.cpu().numpy().astype(np.complex128)
-            num += float(np.sum(np.abs(got - ref) ** 2))
-            den += float(np.sum(np.abs(ref) ** 2))
-        res["rel_l2"] = (num / den) ** 0.5
-    log(f"batched: graph {res['batch_graph']['ms_per_step']:.3f} ms, separate {res['separate_launches']['ms_per_step']:.3f} ms")
-    batch.close()
+            deq = wl.storage_to_complex128(wl.complex_to_storage(p.subgrids, "cbf16"), "cbf16")
+            ref_q, _ = oracle.degrid(deq, p.g_uv.astype(np.float16), p.g_w.astype(np.float16), p.uvw, p.offsets)
+            for key, got, r in (("fp32", g32, ref), ("bf16_vs_fp32_inputs", g16, ref),
+                                ("bf16_vs_stored_inputs", g16, ref_q)):
+                acc[key][0] += float(np.sum(np.abs(got - r) ** 2))
+                acc[key][1] += float(np.sum(np.abs(r) ** 2))
+            worst = max(worst, float(np.max(np.abs(g16 - ref))))
+        res["rel_l2"] = (acc["fp32"][0] / acc["fp32"][1]) ** 0.5
+        res["batch_graph_bf16"]["rel_l2_vs_fp32_inputs"] = (acc["bf16_vs_fp32_inputs"][0] /
+                                                            acc["bf16_vs_fp32_inputs"][1]) ** 0.5
+        res["batch_graph_bf16"]["rel_l2_vs_stored_inputs"] = (acc["bf16_vs_stored_inputs"][0] /
+                                                              acc["bf16_vs_stored_inputs"][1]) ** 0.5
+        res["batch_graph_bf16"]["max_abs_vs_fp32_inputs"] = worst
+    log(f"batched: graph {res['batch_graph']['ms_per_step']:.3f} ms, separate {res['separate_launches']['ms_per_step']:.3f} ms, "
+        f"bf16 graph {res['batch_graph_bf16']['ms_per_step']:.3f} ms")
     return res
 
 

@@ -221,6 +221,20 @@ dg_status degrid_batch_execute(dg_batch b, const void* const* args, hipStream_t 
 /* (DG_ERR_NOT_READY if one of the plans was re-sorted or re-tuned after the
  * batch was planned.) */
 
+/*
+ * Batch autotuner: times every gather kernel variant and tile size on one
+ * launch of the whole batch (the given inputs, as for degrid_batch_execute)
+ * and leaves every plan set to the fastest choice; a batch planned from
+ * these plans afterwards uses it. (The paper picks the visibilities per
+ * block, N_b, by measurement, Section 3.) best_kernel and best_n_b, if not
+ * NULL, receive the choice. Allocates (rebuilds tile lists and builds
+ * trial batches), overwrites the outputs named in args and synchronises the
+ * stream. Batches planned from these plans before the call become stale
+ * (DG_ERR_NOT_READY).
+ */
+dg_status degrid_batch_tune(const dg_plan* plans, int32_t n, const void* const* args, hipStream_t stream,
+                            int32_t* best_kernel, int32_t* best_n_b);
+
 /* Out-of-range count of the batch's last execute. Synchronises its stream. */
 dg_status degrid_batch_oob_count(dg_batch b, int64_t* count);
 

@@ -167,6 +167,7 @@ struct dg_plan_ {
     int32_t cap[kMaxVariants] = {};        // resident workgroups per degrid variant
     int32_t cap_adj[kMaxVariants] = {};    // resident workgroups per adjoint variant
     int32_t device = 0;
+    int32_t n_cu = 0;
     QueueSpec q{};
     DeviceScratch ds;
     hipStream_t last_stream = nullptr;
@@ -279,6 +280,7 @@ dg_status device_capacity(dg_plan_* p) {
         p->cap_adj[v] = std::max(1, n_cu * std::max(1, adj));
     }
     p->device = dev;
+    p->n_cu = n_cu;
     return DG_OK;
 }
 
@@ -487,7 +489,7 @@ dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void*
         hipError_t e = launch_grid_owner(op, p->desc.gcf_dtype, p->own_grid, stream);
         if (e == hipSuccess)
             e = launch_grid_fixup(op.prob, p->d_offsets, p->n_sub, p->offsets.back(), p->d_plan_start, p->ds.ctl,
-                                  p->desc.gcf_dtype, stream);
+                                  p->desc.gcf_dtype, std::max(1, 2 * p->n_cu), stream);
         if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
         p->last_stream = stream;
         p->launched = true;
@@ -781,6 +783,64 @@ dg_status degrid_batch_oob_count(dg_batch b, int64_t* count) {
     e = hipMemcpy(&v, &b->ds.ctl->oob.v[2], sizeof(v), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(out-of-range count)");
     *count = (int64_t)v;
+    return DG_OK;
+}
+
+dg_status degrid_batch_tune(const dg_plan* plans, int32_t n, const void* const* args, hipStream_t stream,
+                            int32_t* best_kernel, int32_t* best_n_b) {
+    if (!plans || n <= 0) return fail(DG_ERR_INVALID_ARG, "need at least one plan");
+    if (!args) return fail(DG_ERR_INVALID_ARG, "args is NULL");
+    for (int32_t i = 0; i < n; ++i)
+        if (!plans[i]) return fail(DG_ERR_INVALID_ARG, "plan %d is NULL", i);
+    static const int32_t kCandidates[] = {8, 16, 32, 64};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    float best_ms = 1e30f;
+    int32_t best_var = plans[0]->variant, best_nb = plans[0]->n_b;
+    dg_status st = DG_OK;
+    for (int var = 0; var < degrid_variant_count() && st == DG_OK; ++var) {
+        int32_t last_nb = -1;
+        for (int32_t nb_req : kCandidates) {
+            const int32_t nb = std::min<int32_t>(nb_req, degrid_variant_max_nb(var));
+            if (nb == last_nb) continue;   // the variant caps the tile size
+            last_nb = nb;
+            for (int32_t i = 0; i < n && st == DG_OK; ++i) {
+                plans[i]->variant = var;
+                st = rebuild_tiles(plans[i], nb, stream);
+            }
+            if (st != DG_OK) break;
+            dg_batch b = nullptr;
+            st = degrid_batch_plan(plans, n, &b);
+            if (st != DG_OK) break;
+            const int reps = 5;
+            for (int r = 0; r < 2 && st == DG_OK; ++r) st = degrid_batch_execute(b, args, stream);
+            (void)hipEventRecord(e0, stream);
+            for (int r = 0; r < reps && st == DG_OK; ++r) st = degrid_batch_execute(b, args, stream);
+            (void)hipEventRecord(e1, stream);
+            he = hipEventSynchronize(e1);
+            (void)degrid_batch_destroy(b);
+            if (st != DG_OK) break;
+            if (he != hipSuccess) { st = hip_fail(he, "hipEventSynchronize"); break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best_var = var; best_nb = nb; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int32_t i = 0; i < n; ++i) {
+        plans[i]->variant = best_var;
+        const dg_status s2 = rebuild_tiles(plans[i], best_nb, stream);
+        if (st == DG_OK) st = s2;
+    }
+    if (st != DG_OK) return st;
+    if (best_kernel) *best_kernel = best_var;
+    if (best_n_b) *best_n_b = best_nb;
     return DG_OK;
 }
 

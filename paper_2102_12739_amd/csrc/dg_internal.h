@@ -42,7 +42,9 @@ struct Problem {
 // each, so atomics from different XCDs do not share a line), the count of
 // finished workgroups, and the out-of-range counters. The last workgroup of
 // every launch resets the cursors and the counters, so a launch needs no
-// separate reset and can be replayed from a graph.
+// separate reset and can be replayed from a graph. (Every workgroup's end is
+// one atomic on the same counter, about 20 ns apiece when they queue, so
+// grids stay near the device's resident capacity.)
 struct alignas(128) CtlLine { uint32_t v[32]; };
 struct Ctl {
     CtlLine cursor[kMaxQueues];
@@ -95,8 +97,11 @@ hipError_t owner_kernel_occupancy(int gcf_kind, int* blocks_per_cu);
 // Adds, with atomics, the visibilities whose first tap differs from the
 // plan's (those the owner pass skipped), and counts out-of-range ones into
 // ctl. n_vis visibilities of one problem; vis_offsets on the device.
+// At most max_blocks workgroups (each one's end is an atomic on the control
+// block, so the grid is kept near the device's resident capacity).
 hipError_t launch_grid_fixup(const Problem& pr, const int64_t* vis_offsets, int64_t n_sub, int64_t n_vis,
-                             const uint32_t* plan_start, Ctl* ctl, int gcf_kind, hipStream_t stream);
+                             const uint32_t* plan_start, Ctl* ctl, int gcf_kind, int max_blocks,
+                             hipStream_t stream);
 // tile_vis[t * kMaxNb + j] = visibility index of item j of tile t: through
 // perms[tile.problem] (a work-order permutation, or nullptr for input order)
 // at position tile.begin + j; items past the tile's count repeat its first.

@@ -452,9 +452,10 @@ hipError_t owner_kernel_occupancy(int gcf_kind, int* n) {
 }
 
 hipError_t launch_grid_fixup(const Problem& pr, const int64_t* vis_offsets, int64_t n_sub, int64_t n_vis,
-                             const uint32_t* plan_start, Ctl* ctl, int gcf_kind, hipStream_t stream) {
+                             const uint32_t* plan_start, Ctl* ctl, int gcf_kind, int max_blocks,
+                             hipStream_t stream) {
     int64_t blocks = (n_vis + kBlockThreads - 1) / kBlockThreads;
-    blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+    blocks = blocks < 1 ? 1 : (blocks > max_blocks ? max_blocks : blocks);
     if (gcf_kind == kGcfF32)
         hipLaunchKernelGGL((grid_fixup_kernel<kGcfF32>), dim3((unsigned)blocks), dim3(kBlockThreads), 0, stream, pr,
                            vis_offsets, n_sub, n_vis, plan_start, ctl);

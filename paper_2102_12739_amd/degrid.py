@@ -85,6 +85,8 @@ def lib():
         "degrid_batch_execute": ([vp, ctypes.POINTER(vp), vp], i32),
         "degrid_batch_oob_count": ([vp, ctypes.POINTER(ctypes.c_int64)], i32),
         "degrid_batch_destroy": ([vp], i32),
+        "degrid_batch_tune": ([ctypes.POINTER(vp), i32, ctypes.POINTER(vp), vp, ctypes.POINTER(i32),
+                               ctypes.POINTER(i32)], i32),
         "degrid_status_str": ([i32], ctypes.c_char_p),
         "degrid_last_error": ([], ctypes.c_char_p),
         "degrid_version": ([], i32),
@@ -256,6 +258,31 @@ class Plan:
             pass
 
 
+def _batch_args(plans, problems, outs):
+    if len(problems) != len(plans):
+        raise ValueError("one (subgrids, g_uv, g_w, uvw) tuple per plan")
+    if outs is None:
+        outs = [torch.empty(p.n_vis, dtype=torch.complex64, device=pr[3].device) for p, pr in zip(plans, problems)]
+    ptrs = []
+    for p, (sub, g_uv, g_w, uvw), out in zip(plans, problems, outs):
+        ptrs += [_ptr(sub, "subgrids", _grid_tensor_dtype(p.grid_dtype), p._grid_shape()),
+                 *p._check_tables(g_uv, g_w), p._check_uvw(uvw),
+                 _ptr(out, "out", torch.complex64, (p.n_vis,))]
+    return (ctypes.c_void_p * len(ptrs))(*ptrs), outs
+
+
+def batch_tune(plans: Sequence[Plan], problems, outs=None, stream=None):
+    """Time kernel variants and tile sizes on one launch of the whole batch and
+    set every plan to the fastest; returns ``(kernel, n_b)``."""
+    plans = list(plans)
+    arr, outs = _batch_args(plans, problems, outs)
+    handles = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+    k, nb = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().degrid_batch_tune(handles, len(plans), arr, _stream_handle(stream), ctypes.byref(k),
+                                   ctypes.byref(nb)), "degrid_batch_tune")
+    return int(k.value), int(nb.value)
+
+
 class Batch:
     """Several plans degridded by one persistent launch replayed from a HIP graph."""
 
@@ -269,17 +296,7 @@ class Batch:
 
     def execute(self, problems, outs=None, stream=None):
         """``problems``: per plan a tuple ``(subgrids, g_uv, g_w, uvw)``; returns the outputs."""
-        if len(problems) != len(self.plans):
-            raise ValueError("one (subgrids, g_uv, g_w, uvw) tuple per plan")
-        if outs is None:
-            outs = [torch.empty(p.n_vis, dtype=torch.complex64, device=pr[3].device)
-                    for p, pr in zip(self.plans, problems)]
-        ptrs = []
-        for p, (sub, g_uv, g_w, uvw), out in zip(self.plans, problems, outs):
-            ptrs += [_ptr(sub, "subgrids", _grid_tensor_dtype(p.grid_dtype), p._grid_shape()),
-                     *p._check_tables(g_uv, g_w), p._check_uvw(uvw),
-                     _ptr(out, "out", torch.complex64, (p.n_vis,))]
-        arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+        arr, outs = _batch_args(self.plans, problems, outs)
         _check(lib().degrid_batch_execute(self._handle, arr, _stream_handle(stream)), "degrid_batch_execute")
         return outs
 

@@ -122,3 +122,35 @@ def test_batch_of_sorted_plans_and_stale_batch_is_refused():
     for p, o in zip(probs, outs):
         ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
         assert rel_l2(o.cpu().numpy(), ref) <= REL_L2_FP32
+
+
+def test_batch_tuner_picks_a_candidate_and_keeps_results():
+    """The batch autotuner times (kernel variant, tile size) candidates on one
+    launch of the whole batch; the batch built after it reproduces the
+    untuned outputs bit for bit (neither choice changes a visibility's sum),
+    and a batch planned before tuning is refused as stale."""
+    from paper_2102_12739_amd.degrid import batch_tune
+    probs = _small_batch(seed=44)
+    announce("batch tuner: " + ", ".join(f"S={p.n_subgrids} N={p.n_vis}" for p in probs))
+    ts = [upload(p) for p in probs]
+    plans = [plan_for(p) for p in probs]
+    for pl, t in zip(plans, ts):
+        pl.sort(t["uvw"])
+    args = [(t["sub"], t["g_uv"], t["g_w"], t["uvw"]) for t in ts]
+    before = Batch(plans)
+    want = [o.cpu().numpy() for o in before.execute(args)]
+    kernel, n_b = batch_tune(plans, args)
+    n_kernels = plans[0].info()["n_kernels"]
+    assert 0 <= kernel < n_kernels and n_b in (8, 16, 32, 64)
+    for pl in plans:
+        info = pl.info()
+        assert info["kernel"] == kernel and info["n_b"] == n_b and info["sorted"] == 1
+    with pytest.raises(DegridError):
+        before.execute(args)
+    before.close()
+    after = Batch(plans)
+    got = [o.cpu().numpy() for o in after.execute(args)]
+    torch.cuda.synchronize()
+    for g, w in zip(got, want):
+        assert np.array_equal(g, w)
+    after.close()
