@@ -492,7 +492,7 @@ def bench_differentiation(steps, warmup, check):
     gridding adjoint through torch.autograd). Also checks, on the GPU
     outputs with float64 sums on the host, the adjoint identity
     <degrid A, V> = <A, grid V> and the gradient against central
-    differences (exact for a quadratic loss) at 16 random points."""
+    differences (exact for a quadratic loss) at 64 random points."""
     import numpy as np
     import torch
     from paper_2102_12739_amd import workload as wl
@@ -552,7 +552,7 @@ def bench_differentiation(steps, warmup, check):
     torch.cuda.synchronize()
     grad = a.grad.detach().reshape(-1).cpu().numpy()
     rng = np.random.default_rng(40)
-    points = rng.choice(grad.size, size=16, replace=False)
+    points = rng.choice(grad.size, size=64, replace=False)
     vo = v_obs_host.astype(np.complex128)
     worst = 0.0
     a0 = a.detach()
@@ -570,7 +570,7 @@ def bench_differentiation(steps, warmup, check):
             g = float(grad[idx].real if part == "re" else grad[idx].imag)
             worst = max(worst, abs(fd - g))
     scale = float(np.max(np.abs(grad)))
-    res["finite_difference"] = {"points": 16, "components": 32, "h": 1.0,
+    res["finite_difference"] = {"points": 64, "components": 128, "h": 1.0,
                                 "max_abs_err": worst, "max_abs_err_over_max_grad": worst / scale}
     if check:
         import oracle
