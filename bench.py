@@ -496,7 +496,7 @@ def bench_differentiation(steps, warmup, check):
     import numpy as np
     import torch
     from paper_2102_12739_amd import workload as wl
-    from paper_2102_12739_amd.degrid import DegridFn, Plan
+    from paper_2102_12739_amd.degrid import DegridFn, Plan, ResidualLossFn
     p = wl.differentiation(seed=4)
     dev = torch.device("cuda:0")
     sub, g_uv, g_w, uvw = upload_inputs(p)
@@ -519,13 +519,23 @@ def bench_differentiation(steps, warmup, check):
         loss = torch.sum(torch.abs(vis - v_obs) ** 2)
         loss.backward()
 
+    def step_fused():
+        a.grad = None
+        loss = ResidualLossFn.apply(a, plan, g_uv, g_w, uvw, v_obs)
+        loss.backward()
+
     out = torch.empty(p.n_vis, dtype=torch.complex64, device=dev)
+    res_buf = torch.empty(p.n_vis, dtype=torch.complex64, device=dev)
+    loss_buf = torch.empty((), dtype=torch.float64, device=dev)
     vin = torch.from_numpy(wl.complex_noise(5, p.n_vis, 1.0).astype(np.complex64)).to(dev)
     gout = torch.empty(plan.shape, dtype=torch.complex64, device=dev)
     res = {"workload": "differentiation-S16-65536-uniform", "visibilities": p.n_vis,
            "v_obs": "oracle degrid of the true subgrids + N(0, 0.01^2) per component" if check
            else "GPU degrid of the true subgrids + N(0, 0.01^2) per component"}
     for name, fn in (("forward_backward", step),
+                     ("fused_forward_backward", step_fused),
+                     ("residual_and_loss", lambda: plan.residual(a.detach(), g_uv, g_w, uvw, v_obs, out=res_buf,
+                                                                 loss=loss_buf)),
                      ("degrid", lambda: plan.execute(sub, g_uv, g_w, uvw, out=out)),
                      ("adjoint", lambda: plan.adjoint(vin, g_uv, g_w, uvw, out=gout))):
         for _ in range(warmup):
@@ -538,6 +548,12 @@ def bench_differentiation(steps, warmup, check):
         ms = (time.perf_counter() - t0) * 1e3 / steps
         res[name] = {"ms_per_step": ms, "value": p.n_vis / (ms * 1e-3)}
     res["adjoint"]["achieved_gbs"] = BYTES_PER_VIS["c64"] * p.n_vis / (res["adjoint"]["ms_per_step"] * 1e-3) / 1e9
+    res["fused_speedup"] = res["forward_backward"]["ms_per_step"] / res["fused_forward_backward"]["ms_per_step"]
+    # the fused loss against the unfused one (float64 sum of the GPU residuals)
+    _, fl = plan.residual(a.detach(), g_uv, g_w, uvw, v_obs)
+    unfused = float(np.sum(np.abs(v_obs_host.astype(np.complex128) -
+                                  plan.execute(a.detach(), g_uv, g_w, uvw).cpu().numpy().astype(np.complex128)) ** 2))
+    res["fused_loss_rel_diff"] = abs(fl.item() - unfused) / unfused
 
     # adjoint identity
     fwd = plan.execute(a.detach(), g_uv, g_w, uvw).cpu().numpy().astype(np.complex128)
@@ -578,7 +594,8 @@ def bench_differentiation(steps, warmup, check):
         ref, _ = oracle.grid(2.0 * (r - vo), p.g_uv, p.g_w, p.uvw, p.offsets, plan.shape)
         got = a.grad.cpu().numpy()
         res["gradient_rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    log(f"differentiation: forward+backward {res['forward_backward']['ms_per_step']:.3f} ms, "
+    log(f"differentiation: forward+backward {res['forward_backward']['ms_per_step']:.3f} ms "
+        f"(fused {res['fused_forward_backward']['ms_per_step']:.3f} ms), "
         f"adjoint {res['adjoint']['ms_per_step']:.3f} ms, identity {res['adjoint_identity_rel']:.2e}, "
         f"fd {res['finite_difference']['max_abs_err_over_max_grad']:.2e}")
     return res

@@ -136,15 +136,36 @@ dg_status degrid_execute(dg_plan p, const void* subgrids, const void* g_uv, cons
                          const double* uvw, void* vis_out, hipStream_t stream);
 
 /*
+ * Residual and loss in the same pass as the degrid (the imaging major cycle
+ * of Section 1 subtracts the model visibilities from the observed ones):
+ *   res_out[i] = v_obs[i] - degrid(subgrids)_i   (complex float32 [N]);
+ *   *loss_out  = sum over all i of |res_out[i]|^2 (float64, device scalar).
+ * An out-of-range visibility has a model of 0, so its residual is v_obs[i].
+ * v_obs and res_out are device complex float32 [N] and may be the same
+ * buffer (in place). Each tile's float64 partial sum is added in a fixed
+ * order, so the loss has the same bits on every call of the same plan (it
+ * may differ in the last bits between plans cut into other tiles). With
+ * no visibilities the loss is written as 0. Other arguments as for
+ * degrid_execute. Asynchronous on 'stream'; allocates nothing.
+ */
+dg_status degrid_residual(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w, const double* uvw,
+                          const void* v_obs, void* res_out, double* loss_out, hipStream_t stream);
+
+/*
  * Adjoint of degrid_execute (gridding): scatters G_w * G_uv * V_i onto the
  * 8 x 8 x 4 neighbourhood of every in-range visibility.
  *   vis          device complex float32 [N].
  *   subgrids_out device complex float32 [S][n_v][n_u][n_w] (always float32,
  *                whatever the plan's grid dtype).
- *   accumulate   0: the output is overwritten (zeroed first, with a kernel);
- *                1: contributions are added to its current contents.
- * Float32 atomics make the summation order, and so the last bits, vary from
- * run to run. Asynchronous on 'stream'; allocates nothing.
+ *   accumulate   0: the output is overwritten; 1: contributions are added to
+ *                its current contents.
+ * On a plan with a work order (degrid_plan_sort), every 16 x 16-cell block
+ * of the output is summed by one wavefront in LDS and written once, so the
+ * result has the same bits on every call; visibilities whose coordinates
+ * moved since the sort are added by a second pass with float32 atomics. On
+ * a plan in input order the output is zeroed (by a kernel) and contributions
+ * are added with float32 atomics, so the last bits vary from run to run.
+ * Asynchronous on 'stream'; allocates nothing.
  */
 dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void* g_w,
                        const double* uvw, void* subgrids_out, int32_t accumulate,

@@ -96,6 +96,7 @@ struct DeviceScratch {
     Tile* tiles = nullptr;
     uint32_t* tile_vis = nullptr;           // [n_tiles][kMaxNb]
     const uint32_t** perm_table = nullptr;  // per problem: work-order permutation or nullptr
+    double* tile_loss = nullptr;            // [n_tiles]: per-tile sums of the residual mode
     Ctl* ctl = nullptr;
     int64_t n_tiles = 0;
     int32_t n_problems = 0;
@@ -105,6 +106,8 @@ void free_tiles(DeviceScratch& ds) {
     if (ds.tiles) (void)hipFree(ds.tiles);
     if (ds.tile_vis) (void)hipFree(ds.tile_vis);
     if (ds.perm_table) (void)hipFree(ds.perm_table);
+    if (ds.tile_loss) (void)hipFree(ds.tile_loss);
+    ds.tile_loss = nullptr;
     ds.tiles = nullptr;
     ds.tile_vis = nullptr;
     ds.perm_table = nullptr;
@@ -134,6 +137,8 @@ dg_status alloc_scratch(DeviceScratch& ds, const std::vector<Tile>& tiles,
         if (e != hipSuccess) { ds.tile_vis = nullptr; return hip_fail(e, "hipMalloc(tile items)"); }
         e = hipMalloc(&ds.perm_table, perms.size() * sizeof(const uint32_t*));
         if (e != hipSuccess) { ds.perm_table = nullptr; return hip_fail(e, "hipMalloc(permutation table)"); }
+        e = hipMalloc(&ds.tile_loss, tiles.size() * sizeof(double));
+        if (e != hipSuccess) { ds.tile_loss = nullptr; return hip_fail(e, "hipMalloc(tile sums)"); }
         e = hipMemcpyAsync(ds.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(ds.perm_table, perms.data(), perms.size() * sizeof(const uint32_t*),
@@ -462,6 +467,29 @@ dg_status degrid_execute(dg_plan p, const void* subgrids, const void* g_uv, cons
     hipError_t e = launch_degrid(params_for(p, pr), p->desc.grid_dtype, p->desc.gcf_dtype, p->variant,
                                  p->blocks, stream);
     if (e != hipSuccess) return hip_fail(e, "degrid kernel launch");
+    p->last_stream = stream;
+    p->launched = true;
+    return DG_OK;
+}
+
+dg_status degrid_residual(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w, const double* uvw,
+                          const void* v_obs, void* res_out, double* loss_out, hipStream_t stream) {
+    if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");
+    if (!loss_out) return fail(DG_ERR_INVALID_ARG, "loss_out is NULL");
+    if (p->ds.n_tiles == 0) {   // no visibilities: the loss is 0
+        hipError_t e = launch_set_f64(loss_out, 0.0, stream);
+        if (e != hipSuccess) return hip_fail(e, "loss fill kernel launch");
+        return DG_OK;
+    }
+    if (!subgrids || !g_uv || !g_w || !uvw || !v_obs || !res_out)
+        return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+    const Problem pr = problem_of(p, subgrids, g_uv, g_w, uvw, res_out, nullptr);
+    LaunchParams lp = params_for(p, pr);
+    lp.v_obs = static_cast<const float2*>(v_obs);
+    lp.tile_loss = p->ds.tile_loss;
+    hipError_t e = launch_degrid(lp, p->desc.grid_dtype, p->desc.gcf_dtype, p->variant, p->blocks, stream);
+    if (e == hipSuccess) e = launch_loss_sum(p->ds.tile_loss, p->ds.n_tiles, loss_out, stream);
+    if (e != hipSuccess) return hip_fail(e, "degrid kernel launch (residual)");
     p->last_stream = stream;
     p->launched = true;
     return DG_OK;

@@ -267,8 +267,22 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
             wn = uvw_n[3 * vis_n + 2];
         }
         wave_lds_sync();
-        if (lane < count)
-            static_cast<float2*>(pr.vis)[vis_c] = in_range ? s_out[wv][lane] : make_float2(0.f, 0.f);
+        double e = 0.0;
+        if (lane < count) {
+            float2 r = in_range ? s_out[wv][lane] : make_float2(0.f, 0.f);
+            if (P.v_obs) {
+                // residual of the observed visibility (it may share memory
+                // with the output: this lane reads, then writes, element vis_c)
+                const float2 o = P.v_obs[vis_c];
+                r = make_float2(o.x - r.x, o.y - r.y);
+                e = (double)r.x * r.x + (double)r.y * r.y;
+            }
+            static_cast<float2*>(pr.vis)[vis_c] = r;
+        }
+        if (P.v_obs) {
+            const double tile_sum = wave_sum_f64(e);
+            if (lane == 0) P.tile_loss[t] = tile_sum;
+        }
         wave_lds_sync();
 
         t = t_nxt;
@@ -280,6 +294,34 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
         w = wn;
     }
     finish_launch(P.ctl, wave_oob);
+}
+
+// Sum of the per-tile loss sums in a fixed order (one workgroup of
+// kLossThreads): thread k adds tiles k, k + kLossThreads, ... in turn
+// (loaded eight at a time, so that the loads overlap), then the wavefront
+// butterfly, then the wavefronts in order. The same bits on every launch.
+constexpr int kLossThreads = 1024;
+__global__ __launch_bounds__(kLossThreads) void loss_sum_kernel(const double* tile_loss, int64_t n, double* loss) {
+    __shared__ double s_part[kLossThreads / kWave];
+    double s = 0.0;
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * (int64_t)kLossThreads) {
+        double x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = i0 + (int64_t)k * kLossThreads;
+            x[k] = i < n ? tile_loss[i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += x[k];
+    }
+    s = wave_sum_f64(s);
+    if (lane_id() == 0) s_part[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double total = 0.0;
+        for (int k = 0; k < kLossThreads / kWave; ++k) total += s_part[k];
+        *loss = total;
+    }
 }
 
 // First tap (y0 << 16 | x0) of the visibility at each position of the work
@@ -302,6 +344,10 @@ __global__ void expand_tiles_kernel(const Tile* tiles, int64_t n_tiles, const ui
     const int64_t pos = tl.begin + (j < tl.count ? j : 0);
     const uint32_t* perm = perms ? perms[tl.problem] : nullptr;
     tile_vis[k] = perm ? perm[pos] : (uint32_t)pos;
+}
+
+__global__ void set_f64_kernel(double* p, double v) {
+    if (threadIdx.x == 0) *p = v;
 }
 
 __global__ void zero_kernel(float4* p, int64_t n) {
@@ -395,6 +441,16 @@ hipError_t launch_expand_tiles(const Tile* tiles, int64_t n_tiles, const uint32_
     const int64_t n = n_tiles * kMaxNb;
     hipLaunchKernelGGL(expand_tiles_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, tiles, n_tiles,
                        perms, tile_vis);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_sum(const double* tile_loss, int64_t n_tiles, double* loss, hipStream_t stream) {
+    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(kLossThreads), 0, stream, tile_loss, n_tiles, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_f64(double* p, double v, hipStream_t stream) {
+    hipLaunchKernelGGL(set_f64_kernel, dim3(1), dim3(64), 0, stream, p, v);
     return hipGetLastError();
 }
 

@@ -357,6 +357,14 @@ __device__ __forceinline__ float4 load_gw_row(uint64_t g_w, int ow) {
 }
 
 
+// Sum over the 64 lanes in float64, in a fixed butterfly order (the same
+// bits on every run).
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+    return x;
+}
+
 // Waits for this wavefront's outstanding vector-memory operations, including
 // loads that write LDS directly.
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }

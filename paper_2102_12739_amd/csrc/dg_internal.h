@@ -59,6 +59,12 @@ struct LaunchParams {
     const uint32_t* tile_vis;   // [n_tiles][kMaxNb]: visibility index of each work item
     Ctl* ctl;
     QueueSpec q;
+    // Residual mode (one problem only; v_obs == nullptr: plain degrid). The
+    // output becomes v_obs - degrid and each tile stores the float64 sum of
+    // |residual|^2 of its visibilities in tile_loss[t] (summed afterwards by
+    // launch_loss_sum).
+    const float2* v_obs;
+    double* tile_loss;
 };
 
 // One output block of the owner-computes adjoint and its visibility list.
@@ -91,6 +97,10 @@ hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int
 hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant, int blocks,
                                hipStream_t stream);
 hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t stream);
+// *loss = sum of tile_loss[0 .. n_tiles) in a fixed order (same bits every time).
+hipError_t launch_loss_sum(const double* tile_loss, int64_t n_tiles, double* loss, hipStream_t stream);
+// *p = v (one float64 written by a kernel, so that graphs may capture it).
+hipError_t launch_set_f64(double* p, double v, hipStream_t stream);
 // Owner-computes adjoint: every output block written once from its list.
 hipError_t launch_grid_owner(const OwnerParams& p, int gcf_kind, int blocks, hipStream_t stream);
 hipError_t owner_kernel_occupancy(int gcf_kind, int* blocks_per_cu);

@@ -74,6 +74,7 @@ def lib():
         "degrid_plan": ([ctypes.POINTER(DgDesc), i64, ctypes.POINTER(ctypes.c_int64), vp,
                          ctypes.POINTER(vp)], i32),
         "degrid_execute": ([vp, vp, vp, vp, vp, vp, vp], i32),
+        "degrid_residual": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "grid_adjoint": ([vp, vp, vp, vp, vp, vp, i32, vp], i32),
         "degrid_oob_count": ([vp, ctypes.POINTER(ctypes.c_int64)], i32),
         "degrid_plan_get_info": ([vp, ctypes.POINTER(DgPlanInfo)], i32),
@@ -191,6 +192,25 @@ class Plan:
         po = _ptr(out, "out", torch.complex64, (self.n_vis,))
         _check(lib().degrid_execute(self._handle, ps, pg, pw, pu, po, _stream_handle(stream)), "degrid_execute")
         return out
+
+    def residual(self, subgrids, g_uv, g_w, uvw, v_obs, out=None, loss=None, stream=None):
+        """``res = v_obs - degrid(subgrids)`` and ``loss = sum |res|^2`` in one pass.
+
+        Returns ``(res complex64 [N], loss float64 0-dim)``; ``out`` may be ``v_obs``.
+        """
+        ps = _ptr(subgrids, "subgrids", _grid_tensor_dtype(self.grid_dtype), self._grid_shape())
+        pg, pw = self._check_tables(g_uv, g_w)
+        pu = self._check_uvw(uvw)
+        pv = _ptr(v_obs, "v_obs", torch.complex64, (self.n_vis,))
+        if out is None:
+            out = torch.empty(self.n_vis, dtype=torch.complex64, device=uvw.device)
+        po = _ptr(out, "out", torch.complex64, (self.n_vis,))
+        if loss is None:
+            loss = torch.empty((), dtype=torch.float64, device=uvw.device)
+        pl = _ptr(loss, "loss", torch.float64, ())
+        _check(lib().degrid_residual(self._handle, ps, pg, pw, pu, pv, po, pl, _stream_handle(stream)),
+               "degrid_residual")
+        return out, loss
 
     def adjoint(self, vis, g_uv, g_w, uvw, out=None, accumulate: bool = False, stream=None) -> torch.Tensor:
         """Grid (transpose of degrid); returns complex64 ``[S, n_v, n_u, n_w]``."""
@@ -339,6 +359,37 @@ class DegridFn(torch.autograd.Function):
         if ctx.needs_input_grad[0]:
             grad = ctx.plan.adjoint(grad_vis.contiguous().to(torch.complex64), g_uv, g_w, uvw)
         return grad, None, None, None, None
+
+
+class ResidualLossFn(torch.autograd.Function):
+    """``loss = sum |v_obs - degrid(subgrids)|^2`` in one fused pass (float64
+    0-dim), with ``d loss / d subgrids = -2 grid_adjoint(res)`` and
+    ``d loss / d v_obs = 2 res`` in PyTorch's complex gradient convention."""
+
+    @staticmethod
+    def forward(ctx, subgrids, plan: Plan, g_uv, g_w, uvw, v_obs):
+        res, loss = plan.residual(subgrids, g_uv, g_w, uvw, v_obs)
+        ctx.plan = plan
+        ctx.save_for_backward(g_uv, g_w, uvw, res)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        g_uv, g_w, uvw, res = ctx.saved_tensors
+        scale = (2.0 * grad_loss).to(torch.float32)
+        grad_sub = grad_obs = None
+        if ctx.needs_input_grad[0]:
+            grad_sub = ctx.plan.adjoint((res * (-scale)).contiguous(), g_uv, g_w, uvw)
+        if ctx.needs_input_grad[5]:
+            grad_obs = res * scale
+        return grad_sub, None, None, None, None, grad_obs
+
+
+def residual_loss(subgrids, g_uv, g_w, uvw, v_obs, plan: Plan) -> torch.Tensor:
+    """Fused ``sum |v_obs - degrid(subgrids)|^2`` with autograd support."""
+    if subgrids.requires_grad or v_obs.requires_grad:
+        return ResidualLossFn.apply(subgrids, plan, g_uv, g_w, uvw, v_obs)
+    return plan.residual(subgrids, g_uv, g_w, uvw, v_obs)[1]
 
 
 def degrid(subgrids, g_uv, g_w, uvw, offsets=None, plan: Plan | None = None, **plan_kw) -> torch.Tensor:
