@@ -198,10 +198,16 @@ def main(argv=None):
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-patterns", action="store_true",
                     help="skip the latency, batched and differentiation measurements")
+    ap.add_argument("--study", action="store_true",
+                    help="instead of the benchmark: the count-scenario x kernel-mapping study (one JSON line)")
     ap.add_argument("--main-only", action="store_true",
                     help="only the timed steps of the sorted plan (for a profiler's per-kernel statistics): "
                          "no input-order run, per-launch distributions, storage variants, CPU baseline or patterns")
     args = ap.parse_args(argv)
+    if args.study:
+        import torch  # noqa: F401
+        print(json.dumps(bench_study(max(args.steps, 5), max(args.warmup, 2))), flush=True)
+        return 0
     if args.main_only:
         args.no_cpu_baseline = args.no_variants = args.no_patterns = True
     if args.gpus != 1:
@@ -650,6 +656,63 @@ def bench_latency(launches=1000, replays=5):
            "label": "latency (launch-bound: the work is a few microseconds)"}
     log(f"latency: graph {res['graph_us_per_launch']['median']:.2f} us/launch, eager {eager_us:.2f} us/launch")
     return res
+
+
+def bench_study(steps, warmup):
+    """The two count scenarios of Section 3 on this GPU: S = 16 subgrids of
+    512 x 512 x 4 with line-shaped visibilities (constant step, as the paper
+    measures), N per subgrid from 2^8 to 2^20, either equal for every subgrid
+    or rising linearly to N in the last one; for each, the gather kernel
+    mappings (through the caches with one or 64 visibilities per tile, and
+    LDS-staged with 12 KiB or 16 KiB boxes), in input order and after the
+    plan-time work order. Median kernel time over the timed launches."""
+    import numpy as np
+    import torch
+    from paper_2102_12739_amd import workload as wl
+    from paper_2102_12739_amd.degrid import Plan
+    dev = torch.device("cuda:0")
+    s_sub = 16
+    base = wl.make_problem("study-grid", [1] * s_sub, seed=7, kind="line")
+    sub = torch.from_numpy(base.subgrids).to(dev)
+    g_uv = torch.from_numpy(base.g_uv).to(dev)
+    g_w = torch.from_numpy(base.g_w).to(dev)
+    mappings = [("cache gather, n_b 1", 0, 1), ("cache gather, n_b 64", 0, 64),
+                ("LDS box 12 KiB, n_b 32", 2, 32), ("LDS box 16 KiB, n_b 64", 4, 64)]
+    rows = []
+    for scenario in ("equal", "ramp"):
+        for e in (8, 10, 12, 14, 16, 18, 20):
+            counts = wl.count_profile(scenario, s_sub, 2 ** e)
+            p = wl.make_problem(f"study-{scenario}-2^{e}", counts, seed=7 + e, kind="line", with_grid=False)
+            uvw = torch.from_numpy(p.uvw).to(dev)
+            out = torch.empty(p.n_vis, dtype=torch.complex64, device=dev)
+            for order in ("input", "sorted"):
+                plan = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w)
+                if order == "sorted":
+                    plan.sort(uvw)
+                for label, var, nb in mappings:
+                    if nb == 1 and 2 ** e > 2 ** 16:
+                        continue   # one tile per visibility: kept to the sizes where it can matter
+                    plan.set_kernel(var, nb)
+                    run = lambda: plan.execute(sub, g_uv, g_w, uvw, out=out)   # noqa: E731
+                    for _ in range(warmup):
+                        run()
+                    ms = percentiles(launch_times(run, steps))["median"]
+                    rows.append({"scenario": scenario, "n_per_subgrid_max": 2 ** e, "visibilities": p.n_vis,
+                                 "order": order, "mapping": label, "kernel": var, "n_b": nb,
+                                 "kernel_us": ms * 1e3, "vis_per_s": p.n_vis / (ms * 1e-3)})
+                    log(f"study {scenario:5s} N=2^{e:<2d} {order:6s} {label:24s} {ms * 1e3:9.1f} us "
+                        f"{p.n_vis / (ms * 1e-3):.3e} vis/s")
+                plan.close()
+            del uvw, out
+            torch.cuda.empty_cache()
+    best = {}
+    for r in rows:
+        k = (r["scenario"], r["n_per_subgrid_max"])
+        if k not in best or r["vis_per_s"] > best[k]["vis_per_s"]:
+            best[k] = r
+    return {"study": "count scenarios x gather mappings (Section 3)", "subgrids": s_sub, "rows": rows,
+            "best": [{"scenario": k[0], "n_per_subgrid_max": k[1], "mapping": v["mapping"], "order": v["order"],
+                      "vis_per_s": v["vis_per_s"]} for k, v in sorted(best.items())]}
 
 
 if __name__ == "__main__":

@@ -313,6 +313,17 @@ def make_problem(name: str, counts, seed: int, kind: str = "mixed",
                    meta={"seed": seed, "kind": kind})
 
 
+def count_profile(scenario: str, s: int, n: int) -> np.ndarray:
+    """Visibilities per subgrid of the two scenarios of Section 3: "equal" gives
+    every subgrid n; "ramp" rises with every subgrid, linearly, up to n in the
+    last one (subgrid k gets round(n * (k + 1) / s))."""
+    if scenario == "equal":
+        return np.full(s, n, dtype=np.int64)
+    if scenario == "ramp":
+        return np.rint(n * (np.arange(s, dtype=np.float64) + 1.0) / s).astype(np.int64)
+    raise ValueError(f"unknown count scenario {scenario!r}")
+
+
 def plain_line(seed: int = 0, with_grid: bool = True) -> Problem:
     """2 subgrids of 512x512x4, 1024 line-shaped visibilities each, os 16."""
     return make_problem("plain-fp32-S2-1024-line", [1024, 1024], seed, "line", with_grid=with_grid)

@@ -92,3 +92,13 @@ def test_storage_round_trip():
     for dt, tol in (("cbf16", 2 ** -8), ("cf16", 2 ** -11)):
         back = wl.storage_to_complex128(wl.complex_to_storage(a, dt), dt)
         assert np.max(np.abs(back - a) / np.maximum(np.abs(a), 1e-3)) <= 2 * tol
+
+
+def test_count_profiles_of_the_two_scenarios():
+    eq = wl.count_profile("equal", 16, 1000)
+    assert eq.shape == (16,) and np.all(eq == 1000)
+    ramp = wl.count_profile("ramp", 16, 1024)
+    assert ramp[-1] == 1024 and ramp[0] == 64
+    assert np.all(np.diff(ramp) > 0)
+    with pytest.raises(ValueError):
+        wl.count_profile("uniform", 4, 8)
