@@ -178,22 +178,16 @@ __global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParam
 // visibility whose first tap at run time differs from the plan's is skipped
 // here; the fix-up pass adds those with atomics.
 
-struct OwnerRec {
-    int32_t x0, y0;   // first tap relative to the block origin (x0 far out of range: skipped)
-    int32_t g_off;    // byte offset of the G_uv block (kOutOfRange if skipped)
-    int32_t pad;
-    float c[8];       // G_w[o_w][t] * V, interleaved (re, im) for t = 0..3
-};
-static_assert(sizeof(OwnerRec) == 48, "OwnerRec layout");
-
 typedef const __attribute__((address_space(4))) OwnerBlock* ConstOwnerBlockPtr;
 
-// This lane's G_uv weights of records j0 .. j0+7 (zero for skipped records).
+// This lane's G_uv weights of items j0 .. j0+7, whose table offsets lane j
+// holds in g_off (kOutOfRange for skipped items: the load returns zero).
 template <int F>
-__device__ __forceinline__ void load_weights8(float* g, const OwnerRec* rec, int j0, __amdgpu_buffer_rsrc_t rg,
+__device__ __forceinline__ void load_weights8(float* g, int g_off, int j0, __amdgpu_buffer_rsrc_t rg,
                                               uint32_t lane_g) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) g[k] = load_gcf_rsrc<F>(rg, (uint32_t)uniform(rec[j0 + k].g_off) + lane_g);
+    for (int k = 0; k < 8; ++k)
+        g[k] = load_gcf_rsrc<F>(rg, (uint32_t)__builtin_amdgcn_readlane(g_off, j0 + k) + lane_g);
 }
 
 // Marks eight values as used here, so that their loads stay where they were
@@ -202,16 +196,20 @@ __device__ __forceinline__ void pin8(float* g) {
     asm volatile("" ::"v"(g[0]), "v"(g[1]), "v"(g[2]), "v"(g[3]), "v"(g[4]), "v"(g[5]), "v"(g[6]), "v"(g[7]));
 }
 
+// First tap of a skipped item, relative to the block: far enough outside
+// that no lane's tap lands in the block.
+constexpr int kSkipX = -1024;
+
 template <int F>
 __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P) {
     constexpr int B = kOwnerBlock;
     constexpr int kCellFloats = kSupportW * 2;          // complex64 x 4 w
     constexpr int kRowFloats = B * kCellFloats;         // floats of one block row
+    constexpr int kRowVec = kRowFloats / 4;             // float4 per block row
     // LDS row pitch: 16 bytes more than a row (cells stay 16-byte aligned and
     // neighbouring rows start on different banks)
     constexpr int kPitch = kRowFloats + 4;
     __shared__ __attribute__((aligned(16))) float s_box[kWavesPerBlock][B * kPitch];
-    __shared__ OwnerRec s_rec[kWavesPerBlock][kWave];
 
     const int lane = lane_id();
     const int wv = (int)(threadIdx.x / kWave);
@@ -237,80 +235,87 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
         float* out = static_cast<float*>(pr.grid_out) +
                      2 * ((int64_t)s * pr.cells_per_sub + ((int64_t)(by * B) * pr.n_u + bx * B) * pr.n_w);
 
-        // the block's current contents (or zeros): one float per lane and step
-#pragma unroll 4
-        for (int f = lane; f < B * kRowFloats; f += kWave) {
-            const int row = f / kRowFloats, col = f - row * kRowFloats;
-            box[row * kPitch + col] = P.accumulate ? out[row * row_floats + col] : 0.0f;
+        // the block's current contents (or zeros), 16 bytes per lane and step
+#pragma unroll
+        for (int f = lane; f < B * kRowVec; f += kWave) {
+            const int row = f / kRowVec, col = f - row * kRowVec;
+            *reinterpret_cast<float4*>(box + row * kPitch + col * 4) =
+                P.accumulate ? *reinterpret_cast<const float4*>(out + row * row_floats + col * 4)
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
         }
+        wave_lds_sync();
 
         for (int c0 = 0; c0 < count; c0 += kWave) {
-            OwnerRec r;
-            r.x0 = -(1 << 20);
-            r.y0 = 0;
-            r.g_off = (int)kOutOfRange;
-            r.pad = 0;
+            // Lane j prepares item c0 + j: its first tap relative to the block
+            // (y in the high, x in the low 16 bits), its G_uv offset and
+            // G_w[o_w][t] * V; the whole wavefront reads them with v_readlane.
+            int32_t xy = kSkipX & 0xFFFF;
+            int32_t g_off = (int)kOutOfRange;
+            float c[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) r.c[q] = 0.0f;
+            for (int q = 0; q < 8; ++q) c[q] = 0.0f;
             if (c0 + lane < count) {
                 const int64_t i = P.items[begin + c0 + lane];
                 const double* uv = pr.uvw + 3 * i;
                 int32_t cell = 0, tab = 0, ow = 0, x0 = 0, y0 = 0;
                 if (coords_from(pr, uv[0], uv[1], uv[2], cell, tab, ow, x0, y0) &&
                     (((uint32_t)y0 << 16) | (uint32_t)x0) == P.plan_start[i]) {
-                    r.x0 = x0 - bx * B;
-                    r.y0 = y0 - by * B;
-                    r.g_off = tab * (int)GcfTraits<F>::kBytes;
+                    xy = (int32_t)((uint32_t)(y0 - by * B) << 16) | ((x0 - bx * B) & 0xFFFF);
+                    g_off = tab * (int)GcfTraits<F>::kBytes;
                     const float2 vv = static_cast<const float2*>(pr.vis)[i];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const float gw = load_gcf<F>(pr.g_w, ow * kSupportW + k);
-                        r.c[2 * k] = gw * vv.x;
-                        r.c[2 * k + 1] = gw * vv.y;
+                        c[2 * k] = gw * vv.x;
+                        c[2 * k + 1] = gw * vv.y;
                     }
                 }
             }
-            s_rec[wv][lane] = r;
-            wave_lds_sync();
             const int n = min(kWave, count - c0);
-            // G_uv weights one group of eight ahead (records past n are
-            // skipped ones, whose loads return zero)
+            // G_uv weights one group of eight ahead (items past n are skipped
+            // ones, whose loads return zero)
             float g[2][8];
-            load_weights8<F>(g[0], s_rec[wv], 0, rg, lane_g);
+            load_weights8<F>(g[0], g_off, 0, rg, lane_g);
 #pragma unroll
             for (int j0 = 0; j0 < kWave; j0 += 8) {
                 if (j0 < n) {
                     float* gc = g[(j0 / 8) & 1];
-                    if (j0 + 8 < kWave) load_weights8<F>(g[((j0 / 8) + 1) & 1], s_rec[wv], j0 + 8, rg, lane_g);
+                    if (j0 + 8 < kWave) load_weights8<F>(g[((j0 / 8) + 1) & 1], g_off, j0 + 8, rg, lane_g);
                     pin8(gc);
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
-                        const OwnerRec& rj = s_rec[wv][j0 + k];
-                        const int cy = rj.y0 + tv, cx = rj.x0 + tu;
+                        const int xyj = __builtin_amdgcn_readlane(xy, j0 + k);
+                        const int cy = (xyj >> 16) + tv;
+                        const int cx = (int)(int16_t)(xyj & 0xFFFF) + tu;
                         if ((unsigned)cy < (unsigned)B && (unsigned)cx < (unsigned)B) {
+                            float cj[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q)
+                                cj[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c[q]), j0 + k));
                             // the taps of one visibility are distinct cells and
                             // LDS operations of a wavefront run in order, so a
                             // plain read-modify-write is exact
                             float4* dst = reinterpret_cast<float4*>(box + cy * kPitch + cx * kCellFloats);
                             float4 a = dst[0], b = dst[1];
-                            a.x += gc[k] * rj.c[0]; a.y += gc[k] * rj.c[1];
-                            a.z += gc[k] * rj.c[2]; a.w += gc[k] * rj.c[3];
-                            b.x += gc[k] * rj.c[4]; b.y += gc[k] * rj.c[5];
-                            b.z += gc[k] * rj.c[6]; b.w += gc[k] * rj.c[7];
+                            a.x += gc[k] * cj[0]; a.y += gc[k] * cj[1];
+                            a.z += gc[k] * cj[2]; a.w += gc[k] * cj[3];
+                            b.x += gc[k] * cj[4]; b.y += gc[k] * cj[5];
+                            b.z += gc[k] * cj[6]; b.w += gc[k] * cj[7];
                             dst[0] = a;
                             dst[1] = b;
                         }
                     }
                 }
             }
-            wave_lds_sync();
         }
+        wave_lds_sync();
 
         // write the block
-#pragma unroll 4
-        for (int f = lane; f < B * kRowFloats; f += kWave) {
-            const int row = f / kRowFloats, col = f - row * kRowFloats;
-            out[row * row_floats + col] = box[row * kPitch + col];
+#pragma unroll
+        for (int f = lane; f < B * kRowVec; f += kWave) {
+            const int row = f / kRowVec, col = f - row * kRowVec;
+            *reinterpret_cast<float4*>(out + row * row_floats + col * 4) =
+                *reinterpret_cast<const float4*>(box + row * kPitch + col * 4);
         }
         wave_lds_sync();
         t = t_next;
