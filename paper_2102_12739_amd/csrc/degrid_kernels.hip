@@ -117,12 +117,21 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
     QueueState st{xcc_id() % P.q.n_queues, 0};
     uint32_t wave_oob = 0;
 
+    // Tiles are taken ahead of need (to hide the queue atomics) only while
+    // the queue holds more tiles after them than there are wavefronts per
+    // queue; near its end each wavefront takes one tile at a time, so that
+    // the last tiles spread over all wavefronts instead of queueing behind
+    // the ones that took tiles early.
+    const int waves_per_queue = ((int)gridDim.x * kWavesPerBlock + P.q.n_queues - 1) / P.q.n_queues;
+    auto ahead_ok = [&](int tile) { return queue_end(P.q, st.q) - tile > waves_per_queue; };
+
+    int t = uniform(pop_tile(P.q, P.ctl, st));
+    while (t >= 0) {
     // current tile and its coordinates (in flight until the loop needs them)
-    int t = pop_tile(P.q, P.ctl, st);
     Tile tc{};
     int64_t vis_c = 0;
     double u = 0.0, v = 0.0, w = 0.0;
-    if (t >= 0) {
+    {
         tc = load_tile(P.tiles, t);
         vis_c = P.tile_vis[(int64_t)t * kMaxNb + lane];
         const double* uvw = problem_uvw(P, tc.problem);
@@ -132,7 +141,7 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
             w = uvw[3 * vis_c + 2];
         }
     }
-    int t_nxt = t >= 0 ? pop_tile(P.q, P.ctl, st) : -1;
+    int t_nxt = uniform(ahead_ok(t) ? pop_tile(P.q, P.ctl, st) : -1);
     // pop of the tile after t_nxt, sent during the previous tile
     bool pend = false;
     uint32_t raw = 0;
@@ -158,9 +167,13 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
         }
         // (wave-uniform: both pops return a readfirstlane value; stated so
         // that the tile descriptors derived from it stay in scalar registers)
-        const int t_after =
-            uniform(!has_next ? -1 : (pend ? pop_resolve(P.q, P.ctl, st, raw) : pop_tile(P.q, P.ctl, st)));
+        const int t_after = uniform(!has_next ? -1
+                                              : (pend ? pop_resolve(P.q, P.ctl, st, raw)
+                                                      : (ahead_ok(t_nxt) ? pop_tile(P.q, P.ctl, st) : -1)));
         pend = false;
+        // the pop of the tile after next is sent during this tile (below)
+        // only when that one is not among the queue's last tiles
+        const bool send_ahead = t_after >= 0 && ahead_ok(t_after);
 
         const char* sub_base = static_cast<const char*>(pr.subgrids) + (int64_t)tc.sub * pr.sub_bytes;
         const __amdgpu_buffer_rsrc_t ra = make_rsrc(sub_base, pr.sub_bytes);
@@ -232,7 +245,7 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
             wait_vmem();
             wave_lds_sync();
             // the pop of the tile after next travels while this tile is gathered
-            if (t_after >= 0) {
+            if (send_ahead) {
                 raw = pop_issue(P.ctl, st);
                 pend = true;
             }
@@ -256,7 +269,7 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
             gather_tile<G, F, NB, true, kPlane1>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
         } else {
             gather_tile<G, F, NB, false, kPlane1>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
-            if (t_after >= 0) {
+            if (send_ahead) {
                 raw = pop_issue(P.ctl, st);
                 pend = true;
             }
@@ -292,6 +305,9 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
         u = un;
         v = vn;
         w = wn;
+    }
+    // the look-ahead stopped (or the queues are empty): take the next tile now
+    t = uniform(pop_tile(P.q, P.ctl, st));
     }
     finish_launch(P.ctl, wave_oob);
 }

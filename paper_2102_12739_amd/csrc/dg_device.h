@@ -73,6 +73,16 @@ __device__ __forceinline__ int pop_tile(const QueueSpec& qs, Ctl* ctl, QueueStat
     return -1;
 }
 
+// One past the last tile of queue q (the selection keeps the queue table in
+// scalar registers).
+__device__ __forceinline__ int queue_end(const QueueSpec& qs, int q) {
+    int e = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxQueues; ++k)
+        if (q == k) e = qs.end[k];
+    return e;
+}
+
 // The two halves of a pop whose atomic is left in flight while the
 // wavefront works: pop_issue sends the cursor increment of the current queue
 // and returns without waiting; pop_resolve (called later) turns the returned

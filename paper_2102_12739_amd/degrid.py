@@ -393,12 +393,17 @@ def residual_loss(subgrids, g_uv, g_w, uvw, v_obs, plan: Plan) -> torch.Tensor:
 
 
 def degrid(subgrids, g_uv, g_w, uvw, offsets=None, plan: Plan | None = None, **plan_kw) -> torch.Tensor:
-    """Degrid with autograd support (differentiable with respect to ``subgrids``)."""
+    """Degrid with autograd support (differentiable with respect to ``subgrids``).
+
+    A plan made here gets the plan-time work order of ``uvw`` (``Plan.sort``),
+    which the gridding adjoint of the backward needs to run without global
+    atomics."""
     if plan is None:
         if offsets is None:
             raise ValueError("give offsets or a plan")
         s, n_v, n_u, n_w = subgrids.shape[:4]
         plan = Plan(offsets, n_v, n_u, n_w, os_uv=g_uv.shape[0], os_w=g_w.shape[0], **plan_kw)
+        plan.sort(uvw)
     if subgrids.requires_grad:
         return DegridFn.apply(subgrids, plan, g_uv, g_w, uvw)
     return plan.execute(subgrids, g_uv, g_w, uvw)
@@ -411,4 +416,5 @@ def grid_adjoint(vis, g_uv, g_w, uvw, offsets=None, shape=None, plan: Plan | Non
             raise ValueError("give offsets and shape, or a plan")
         s, n_v, n_u, n_w = shape
         plan = Plan(offsets, n_v, n_u, n_w, os_uv=g_uv.shape[0], os_w=g_w.shape[0], **plan_kw)
+        plan.sort(uvw)
     return plan.adjoint(vis, g_uv, g_w, uvw)
