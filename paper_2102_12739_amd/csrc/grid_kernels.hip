@@ -220,14 +220,18 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
     const uint32_t lane_g = (uint32_t)lane * GcfTraits<F>::kBytes;
     const int64_t row_floats = 2 * (int64_t)pr.n_u * pr.n_w;   // floats per subgrid row
     float* box = s_box[wv];
+    // the next block is taken at the start of a block only while its queue
+    // holds more blocks than wavefronts per queue (else after the block)
+    const int waves_per_queue = ((int)gridDim.x * kWavesPerBlock + P.q.n_queues - 1) / P.q.n_queues;
 
-    int t = pop_tile(P.q, P.ctl, st);
+    int t = uniform(pop_tile(P.q, P.ctl, st));
     while (t >= 0) {
         const ConstOwnerBlockPtr pb = (ConstOwnerBlockPtr)uniform_u64((uint64_t)P.blocks) + t;
         const int64_t begin = pb->begin;
         const int count = pb->count;
         const int blk = pb->block;
-        const int t_next = pop_tile(P.q, P.ctl, st);
+        const bool ahead = queue_end(P.q, st.q) - t > waves_per_queue;
+        const int t_next = uniform(ahead ? pop_tile(P.q, P.ctl, st) : -1);
         const int per_sub = P.nby * P.nbx;
         const int s = blk / per_sub;
         const int by = (blk - s * per_sub) / P.nbx;
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
                 *reinterpret_cast<const float4*>(box + row * kPitch + col * 4);
         }
         wave_lds_sync();
-        t = t_next;
+        t = ahead ? t_next : uniform(pop_tile(P.q, P.ctl, st));
     }
     finish_launch(P.ctl, 0u);
 }
