@@ -20,9 +20,12 @@
  *   - subgrid layout [S][n_v][n_u][n_w], w fastest, complex interleaved
  *     (re, im);
  *   - [u, v, w] are float64 in subgrid cells, origin at cell 0; per axis
- *     k = floor(c * os) (exact in float64, os a power of two), cell
- *     n = floor(k / os), oversample index o = k - n * os, first tap
+ *     k = floor(c * os) of the float64 product (exact when os is a power of
+ *     two; for other factors this rounding of the product is the contract),
+ *     cell n = floor(k / os), oversample index o = k - n * os, first tap
  *     n - (W/2 - 1);
+ *   - subgrids may hold more w planes than the w support (n_w > 4): the
+ *     first w tap z = floor(w) - 1 then varies between visibilities;
  *   - G_uv is indexed [o_v][o_u][t_v][t_u], G_w is indexed [o_w][t_w]; both
  *     real;
  *   - a visibility whose neighbourhood leaves the subgrid (or whose
@@ -79,9 +82,9 @@ typedef enum {
 
 /* Problem descriptor (Section 2: subgrid size, GCF supports and oversampling). */
 typedef struct {
-    int32_t n_v, n_u, n_w;          /* subgrid size; the paper's is 512, 512, 4                    */
+    int32_t n_v, n_u, n_w;          /* subgrid size; the paper's is 512, 512, 4; n_w >= 4          */
     int32_t support_uv, support_w;  /* GCF supports; must be 8 and 4 (else DG_ERR_UNSUPPORTED)     */
-    int32_t os_uv, os_w;            /* oversampling, powers of two in [1, 64]; tables are          */
+    int32_t os_uv, os_w;            /* oversampling factors in [1, 64]; tables are                 */
                                     /* G_uv[os_uv][os_uv][8][8] and G_w[os_w][4]                   */
     int32_t grid_dtype;             /* dg_grid_dtype                                               */
     int32_t gcf_dtype;              /* dg_gcf_dtype                                                */
@@ -116,7 +119,10 @@ typedef struct {
  * Allocates device scratch on the current HIP device. Synchronises 'stream'.
  * Returns DG_ERR_INVALID_ARG for a bad descriptor or offsets,
  * DG_ERR_UNSUPPORTED for supports other than 8 x 8 and 4, DG_ERR_NOMEM or
- * DG_ERR_HIP when the device side cannot be set up.
+ * DG_ERR_HIP when the device side cannot be set up. A plan for subgrids with
+ * n_w != 4 uses the one kernel variant that reads taps starting at any w
+ * (no LDS staging); degrid_plan_set_kernel refuses the others for it, and
+ * its adjoint scatters with float32 atomics even after degrid_plan_sort.
  */
 dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_offsets,
                       hipStream_t stream, dg_plan* out);

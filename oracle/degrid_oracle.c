@@ -20,9 +20,10 @@
  * design notes of the repository):
  *   - subgrid memory order [S][v][u][w], w fastest, complex interleaved;
  *   - coordinates in subgrid cells with the origin at cell 0;
- *   - per axis, k = floor(c * os) (exact in FP64 for os = 2^m), the cell
- *     n = floor(k / os), the oversample index o = k - n * os, and the first
- *     tap n - (W/2 - 1);
+ *   - per axis, k = floor(c * os) of the FP64 product (exact for os = 2^m;
+ *     for other factors the rounding of the product is part of the
+ *     definition), the cell n = floor(k / os), the oversample index
+ *     o = k - n * os, and the first tap n - (W/2 - 1);
  *   - G_uv indexed [o_v][o_u][t_v][t_u], G_w indexed [o_w][t_w];
  *   - a neighbourhood that would leave the subgrid is not wrapped or
  *     clamped: the visibility is 0 and is counted as out of range;

@@ -64,11 +64,8 @@ dg_status validate_desc(const dg_desc* d) {
                     "supports must be 8 (uv) and 4 (w), got %d and %d", d->support_uv, d->support_w);
     if (d->n_v < kSupportUV || d->n_u < kSupportUV || d->n_w < kSupportW)
         return fail(DG_ERR_INVALID_ARG, "subgrid %dx%dx%d is smaller than the support", d->n_v, d->n_u, d->n_w);
-    if (d->n_w != kSupportW)
-        return fail(DG_ERR_UNSUPPORTED, "n_w must equal the w support (4), got %d", d->n_w);
-    if (log2_exact(d->os_uv) < 0 || d->os_uv > 64 || log2_exact(d->os_w) < 0 || d->os_w > 64)
-        return fail(DG_ERR_INVALID_ARG, "oversampling must be a power of two in [1, 64], got %d and %d",
-                    d->os_uv, d->os_w);
+    if (d->os_uv < 1 || d->os_uv > 64 || d->os_w < 1 || d->os_w > 64)
+        return fail(DG_ERR_INVALID_ARG, "oversampling must be in [1, 64], got %d and %d", d->os_uv, d->os_w);
     if (d->grid_dtype < DG_GRID_C64 || d->grid_dtype > DG_GRID_CF16)
         return fail(DG_ERR_INVALID_ARG, "unknown grid dtype %d", d->grid_dtype);
     if (d->gcf_dtype < DG_GCF_F32 || d->gcf_dtype > DG_GCF_F16)
@@ -211,6 +208,7 @@ void free_owner(dg_plan_* p) {
 
 struct dg_batch_ {
     std::vector<dg_plan> plans;
+    int32_t variant = 0;                 // kernel of the batch launch
     std::vector<uint64_t> plan_versions;
     int32_t grid_dtype = 0, gcf_dtype = 0;
     int32_t device = 0;
@@ -247,6 +245,8 @@ Problem problem_of(const dg_plan_* p, const void* subgrids, const void* g_uv, co
     pr.n_w = d.n_w;
     pr.log2_os_uv = log2_exact(d.os_uv);
     pr.log2_os_w = log2_exact(d.os_w);
+    pr.os_uv = d.os_uv;
+    pr.os_w = d.os_w;
     pr.guv_bytes = (uint32_t)d.os_uv * d.os_uv * kSupportUV * kSupportUV * gcf_elem_bytes(d.gcf_dtype);
     pr.sub_bytes = (uint32_t)(pr.cells_per_sub * grid_elem_bytes(d.grid_dtype));
     // in range: first tap >= 0 and last tap < n along each axis
@@ -330,6 +330,11 @@ void tune_cache_store(const std::string& key, int32_t n_b, int32_t variant) {
 // cache fixes them.
 constexpr int32_t kDefaultNb = 64;
 constexpr int32_t kDefaultVariant = 4;
+
+// Subgrids with more w planes than the w support have taps that start at any
+// w: only the deep variant (no staging, one load per w value) reads them.
+bool deep_only(const dg_desc& d) { return d.n_w != kSupportW; }
+bool variant_allowed(const dg_desc& d, int v) { return !deep_only(d) || v == kDeepVariant; }
 
 // Smallest tile worth staging when tiles are cut to fit the box.
 constexpr int kMinStagedTile = 16;
@@ -444,6 +449,7 @@ dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_o
     p->offsets.assign(vis_offsets, vis_offsets + n_subgrids + 1);
     int32_t n_b = d->n_b, variant = kDefaultVariant;
     if (n_b == 0 && !tune_cache_lookup(tune_key(p), &n_b, &variant)) n_b = kDefaultNb;
+    if (!variant_allowed(*d, variant)) variant = kDeepVariant;
     p->variant = variant;
     s = device_capacity(p);
     if (s == DG_OK) s = rebuild_tiles(p, n_b, stream);
@@ -581,6 +587,7 @@ dg_status degrid_tune(dg_plan p, const void* subgrids, const void* g_uv, const v
     int32_t best_nb = p->n_b, best_var = p->variant;
     dg_status st = DG_OK;
     for (int var = 0; var < degrid_variant_count() && st == DG_OK; ++var) {
+        if (!variant_allowed(p->desc, var)) continue;
         for (int32_t nb : kCandidates) {
             p->variant = var;
             st = rebuild_tiles(p, nb, stream);
@@ -653,7 +660,8 @@ dg_status degrid_plan_sort(dg_plan p, const double* uvw, hipStream_t stream) {
         p->start.clear();
         return hip_fail(e, "computing start cells");
     }
-    dg_status st = build_owner(p, stream);
+    // owner-computes gridding keeps 4 w values per cell in LDS
+    dg_status st = deep_only(p->desc) ? DG_OK : build_owner(p, stream);
     if (st != DG_OK) return st;
     return rebuild_tiles(p, p->n_b_req, stream);
 }
@@ -663,6 +671,9 @@ dg_status degrid_plan_set_kernel(dg_plan p, int32_t kernel, int32_t n_b, hipStre
     if (kernel < -1 || kernel >= degrid_variant_count())
         return fail(DG_ERR_INVALID_ARG, "kernel must be in [-1, %d), got %d", degrid_variant_count(), kernel);
     if (n_b < 0 || n_b > kMaxNb) return fail(DG_ERR_INVALID_ARG, "n_b must be in [0, %d], got %d", kMaxNb, n_b);
+    if (kernel >= 0 && !variant_allowed(p->desc, kernel))
+        return fail(DG_ERR_UNSUPPORTED, "subgrids with %d w planes need kernel %d (got %d)", p->desc.n_w,
+                    kDeepVariant, kernel);
     if (kernel >= 0) p->variant = kernel;
     return rebuild_tiles(p, n_b > 0 ? n_b : p->n_b_req, stream);
 }
@@ -694,10 +705,15 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
     if (!b) return fail(DG_ERR_NOMEM, "host allocation of the batch failed");
     b->plans.assign(plans, plans + n);
     for (int32_t i = 0; i < n; ++i) b->plan_versions.push_back(plans[i]->version);
+    // one kernel for the whole batch: plan 0's, or the deep one if any plan
+    // has subgrids deeper than the w support
+    b->variant = plans[0]->variant;
+    for (int32_t i = 0; i < n; ++i)
+        if (deep_only(plans[i]->desc)) b->variant = kDeepVariant;
     b->grid_dtype = plans[0]->desc.grid_dtype;
     b->gcf_dtype = plans[0]->desc.gcf_dtype;
     b->device = plans[0]->device;
-    const int max_nb = degrid_variant_max_nb(plans[0]->variant);
+    const int max_nb = degrid_variant_max_nb(b->variant);
     std::vector<Tile> tiles;
     std::vector<const uint32_t*> perms;
     for (int32_t i = 0; i < n; ++i) {
@@ -721,7 +737,7 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
     s = alloc_scratch(b->ds, tiles, perms, nullptr);
     if (s != DG_OK) return bail(s);
     b->q = split_queues(tiles);
-    b->blocks = blocks_for(plans[0]->cap[plans[0]->variant], b->ds.n_tiles);
+    b->blocks = blocks_for(plans[0]->cap[b->variant], b->ds.n_tiles);
     e = hipMalloc(&b->d_probs, sizeof(Problem) * n);
     if (e != hipSuccess) { b->d_probs = nullptr; return bail(hip_fail(e, "hipMalloc(problem table)")); }
     e = hipHostMalloc(&b->h_probs, sizeof(Problem) * n, hipHostMallocDefault);
@@ -744,7 +760,7 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
         if (e != hipSuccess) return bail(hip_fail(e, "hipStreamCreate"));
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = launch_degrid(lp, b->grid_dtype, b->gcf_dtype, plans[0]->variant, b->blocks, cap);
+            hipError_t le = launch_degrid(lp, b->grid_dtype, b->gcf_dtype, b->variant, b->blocks, cap);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(cap, &g);
             if (le != hipSuccess) e = le;
@@ -831,7 +847,10 @@ dg_status degrid_batch_tune(const dg_plan* plans, int32_t n, const void* const* 
     float best_ms = 1e30f;
     int32_t best_var = plans[0]->variant, best_nb = plans[0]->n_b;
     dg_status st = DG_OK;
+    bool any_deep = false;
+    for (int32_t i = 0; i < n; ++i) any_deep = any_deep || deep_only(plans[i]->desc);
     for (int var = 0; var < degrid_variant_count() && st == DG_OK; ++var) {
+        if (any_deep && var != kDeepVariant) continue;
         int32_t last_nb = -1;
         for (int32_t nb_req : kCandidates) {
             const int32_t nb = std::min<int32_t>(nb_req, degrid_variant_max_nb(var));

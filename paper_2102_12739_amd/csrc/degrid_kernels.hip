@@ -41,7 +41,7 @@ struct Fetch8 {
 // Lane j holds the coordinate-stage results of visibility j: a_off (byte
 // offset of its first tap in the LDS box or in the subgrid) and ow (its G_w
 // row); v_readlane hands them to the whole wavefront.
-template <int G, bool STAGED, uint32_t PLANE1>
+template <int G, bool STAGED, uint32_t PLANE1, bool DEEP>
 __device__ __forceinline__ void fetch8(Fetch8<G>& f, int g0, int a_off, __amdgpu_buffer_rsrc_t ra,
                                        uint32_t lane_a, const char* box) {
 #pragma unroll
@@ -49,6 +49,8 @@ __device__ __forceinline__ void fetch8(Fetch8<G>& f, int g0, int a_off, __amdgpu
         const uint32_t aj = (uint32_t)__builtin_amdgcn_readlane(a_off, g0 + k);
         if constexpr (STAGED) {
             lds_w4<G, PLANE1>(box, lane_a + aj, f.raw[k]);
+        } else if constexpr (DEEP) {
+            load_w4_narrow<G>(ra, lane_a + aj, f.raw[k]);
         } else {
             load_w4<G>(ra, lane_a + aj, f.raw[k]);
         }
@@ -79,17 +81,17 @@ __device__ __forceinline__ void sum8(const Fetch8<G>& f, const float* gv, int ow
 }
 
 // All visibilities of a tile, groups of eight in a two-stage pipeline.
-template <int G, int F, int NB, bool STAGED, uint32_t PLANE1>
+template <int G, int F, int NB, bool STAGED, uint32_t PLANE1, bool DEEP>
 __device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, int ow, const float* gv,
                                             __amdgpu_buffer_rsrc_t ra, uint64_t g_w, uint32_t lane_a,
                                             const char* box) {
     Fetch8<G> buf[2];
-    fetch8<G, STAGED, PLANE1>(buf[0], 0, a_off, ra, lane_a, box);
+    fetch8<G, STAGED, PLANE1, DEEP>(buf[0], 0, a_off, ra, lane_a, box);
 #pragma unroll
     for (int g0 = 0; g0 < NB; g0 += 8) {
         if (g0 < count) {
             if (g0 + 8 < NB && g0 + 8 < count)
-                fetch8<G, STAGED, PLANE1>(buf[((g0 / 8) + 1) & 1], g0 + 8, a_off, ra, lane_a, box);
+                fetch8<G, STAGED, PLANE1, DEEP>(buf[((g0 / 8) + 1) & 1], g0 + 8, a_off, ra, lane_a, box);
             sum8<G, F>(buf[(g0 / 8) & 1], gv + g0, ow, g_w, out, g0);
         }
     }
@@ -103,7 +105,7 @@ __device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, i
 // next tile's header and visibility indices are requested when the current
 // tile starts, its coordinates while the current tile is gathered, and the
 // tile after it is popped from the queue one tile ahead.
-template <int G, int F, int BOX, int NB>
+template <int G, int F, int BOX, int NB, bool DEEP>
 __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P) {
     using GT = GridTraits<G>;
     static_assert(NB % 8 == 0 && NB <= kMaxNb, "tile size");
@@ -195,8 +197,9 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
 
         bool staged = false;
         int bx0 = 0, by0 = 0, bw = 0, bh = 0, bp = 0;
-        if constexpr (BOX > 0) {
-            // bounding box of the tile's neighbourhoods
+        if (BOX > 0 && pr.n_w == kSupportW) {
+            // bounding box of the tile's neighbourhoods (the box holds w 0..3
+            // of each cell, so only subgrids of 4 w planes are staged)
             bx0 = uniform(wave_min(in_range ? x0 : 0x7FFFFFFF));
             by0 = uniform(wave_min(in_range ? y0 : 0x7FFFFFFF));
             const int bx1 = uniform(wave_max(in_range ? x0 : -1));
@@ -266,9 +269,9 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
         const uint32_t lane_a = staged ? ((uint32_t)(lane >> 3) * bp + (lane & 7)) * 16u
                                        : (uint32_t)(((lane >> 3) * pr.n_u + (lane & 7)) * pr.n_w) * GT::kElemBytes;
         if (staged) {
-            gather_tile<G, F, NB, true, kPlane1>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
+            gather_tile<G, F, NB, true, kPlane1, false>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
         } else {
-            gather_tile<G, F, NB, false, kPlane1>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
+            gather_tile<G, F, NB, false, kPlane1, DEEP>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
             if (send_ahead) {
                 raw = pop_issue(P.ctl, st);
                 pend = true;
@@ -374,15 +377,15 @@ __global__ void zero_kernel(float4* p, int64_t n) {
 
 template <int G, int F, int V>
 hipError_t launch_degrid_t(const LaunchParams& p, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((degrid_kernel<G, F, kVariants[V].box, kVariants[V].nb>), dim3(blocks), dim3(kBlockThreads),
-                       0, s, p);
+    hipLaunchKernelGGL((degrid_kernel<G, F, kVariants[V].box, kVariants[V].nb, kVariants[V].deep>), dim3(blocks),
+                       dim3(kBlockThreads), 0, s, p);
     return hipGetLastError();
 }
 
 template <int G, int F, int V>
 hipError_t occ_degrid_t(int* n) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, degrid_kernel<G, F, kVariants[V].box, kVariants[V].nb>,
-                                                        kBlockThreads, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        n, degrid_kernel<G, F, kVariants[V].box, kVariants[V].nb, kVariants[V].deep>, kBlockThreads, 0);
 }
 
 template <int G, int F>
@@ -393,6 +396,7 @@ hipError_t launch_degrid_v(const LaunchParams& p, int variant, int blocks, hipSt
         case 2: return launch_degrid_t<G, F, 2>(p, blocks, s);
         case 3: return launch_degrid_t<G, F, 3>(p, blocks, s);
         case 4: return launch_degrid_t<G, F, 4>(p, blocks, s);
+        case 5: return launch_degrid_t<G, F, 5>(p, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -405,6 +409,7 @@ hipError_t occ_degrid_v(int variant, int* n) {
         case 2: return occ_degrid_t<G, F, 2>(n);
         case 3: return occ_degrid_t<G, F, 3>(n);
         case 4: return occ_degrid_t<G, F, 4>(n);
+        case 5: return occ_degrid_t<G, F, 5>(n);
         default: return hipErrorInvalidValue;
     }
 }

@@ -154,6 +154,24 @@ __device__ __forceinline__ void load_w4(__amdgpu_buffer_rsrc_t r, uint32_t off,
     }
 }
 
+// The same with one load per w value (8 bytes for complex64, 4 otherwise), so
+// that the loads are naturally aligned whatever the first w of the tap.
+template <int G>
+__device__ __forceinline__ void load_w4_narrow(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                               uint32_t (&raw)[GridTraits<G>::kWords]) {
+    if constexpr (G == kGridC64) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            auto a = __builtin_amdgcn_raw_buffer_load_b64(r, off + 8u * (uint32_t)t, 0, 0);
+            raw[2 * t] = a[0];
+            raw[2 * t + 1] = a[1];
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) raw[t] = __builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * (uint32_t)t, 0, 0);
+    }
+}
+
 // Widen the 4 w values of one tap to float32 (re[t], im[t]).
 template <int G>
 __device__ __forceinline__ void widen_w4(const uint32_t (&raw)[GridTraits<G>::kWords],
@@ -214,22 +232,38 @@ __device__ __forceinline__ float load_gcf(const void* table, int64_t idx) {
 // neighbourhood leaves the subgrid or the coordinate is not finite.
 __device__ __forceinline__ bool coords_from(const Problem& pr, double u, double v, double w, int32_t& cell,
                                             int32_t& tab, int32_t& ow, int32_t& x_start, int32_t& y_start) {
-    const bool ok = (u >= 3.0) & (u < pr.hi_u) & (v >= 3.0) & (v < pr.hi_v) &
-                    (w >= 1.0) & (w < pr.hi_w);
-    if (!ok) return false;
-    const int os_uv = 1 << pr.log2_os_uv;
-    const int os_w = 1 << pr.log2_os_w;
-    const int ku = (int)(u * (double)os_uv);   // non-negative: truncation is floor
+    // coarse float64 bounds first (they also reject NaN and values too large
+    // for an int), then the exact test on the cells
+    const bool near = (u >= 2.0) & (u < pr.hi_u + 1.0) & (v >= 2.0) & (v < pr.hi_v + 1.0) &
+                      (w >= 0.0) & (w < pr.hi_w + 1.0);
+    if (!near) return false;
+    const int os_uv = pr.os_uv;
+    const int os_w = pr.os_w;
+    // k = floor(c * os) of the float64 product (exact when os is a power of
+    // two); non-negative, so truncation is floor
+    const int ku = (int)(u * (double)os_uv);
     const int kv = (int)(v * (double)os_uv);
     const int kw = (int)(w * (double)os_w);
-    const int x0 = (ku >> pr.log2_os_uv) - (kSupportUV / 2 - 1);
-    const int y0 = (kv >> pr.log2_os_uv) - (kSupportUV / 2 - 1);
-    const int z0 = (kw >> pr.log2_os_w) - (kSupportW / 2 - 1);
-    const int ou = ku & (os_uv - 1);
-    const int ov = kv & (os_uv - 1);
-    ow = kw & (os_w - 1);
+    int nu, nv, nw;
+    if (pr.log2_os_uv >= 0) {
+        nu = ku >> pr.log2_os_uv;
+        nv = kv >> pr.log2_os_uv;
+    } else {
+        nu = ku / os_uv;
+        nv = kv / os_uv;
+    }
+    nw = pr.log2_os_w >= 0 ? kw >> pr.log2_os_w : kw / os_w;
+    const int x0 = nu - (kSupportUV / 2 - 1);
+    const int y0 = nv - (kSupportUV / 2 - 1);
+    const int z0 = nw - (kSupportW / 2 - 1);
+    if ((x0 < 0) | (x0 > pr.n_u - kSupportUV) | (y0 < 0) | (y0 > pr.n_v - kSupportUV) | (z0 < 0) |
+        (z0 > pr.n_w - kSupportW))
+        return false;
+    const int ou = ku - nu * os_uv;
+    const int ov = kv - nv * os_uv;
+    ow = kw - nw * os_w;
     cell = (y0 * pr.n_u + x0) * pr.n_w + z0;
-    tab = ((ov << pr.log2_os_uv) + ou) * (kSupportUV * kSupportUV);
+    tab = (ov * os_uv + ou) * (kSupportUV * kSupportUV);
     x_start = x0;
     y_start = y0;
     return true;
@@ -338,6 +372,8 @@ __device__ __forceinline__ Problem load_problem(const Problem* probs, int i) {
     x.n_w = p->n_w;
     x.log2_os_uv = p->log2_os_uv;
     x.log2_os_w = p->log2_os_w;
+    x.os_uv = p->os_uv;
+    x.os_w = p->os_w;
     x.guv_bytes = p->guv_bytes;
     x.sub_bytes = p->sub_bytes;
     x.hi_u = p->hi_u;
@@ -394,10 +430,14 @@ __device__ __forceinline__ void lds_w4(const char* box, uint32_t off, uint32_t (
     }
 }
 
-// Kernel variants: (LDS box per wavefront in bytes, largest tile). Box 0
-// gathers through the caches only.
-struct Variant { int box; int nb; };
-constexpr Variant kVariants[] = {{0, 64}, {8192, 32}, {12288, 32}, {16384, 32}, {16384, 64}};
+// Kernel variants: (LDS box per wavefront in bytes, largest tile, deep).
+// Box 0 gathers through the caches only. A deep variant reads the 4 w values
+// of a tap with loads of one value each (naturally aligned at any first w),
+// for subgrids with more w planes than the w support; it never stages.
+struct Variant { int box; int nb; bool deep; };
+constexpr Variant kVariants[] = {{0, 64, false},     {8192, 32, false},  {12288, 32, false},
+                                 {16384, 32, false}, {16384, 64, false}, {0, 64, true}};
+static_assert(kVariants[kDeepVariant].deep && kVariants[kDeepVariant].box == 0, "deep variant index");
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 }  // namespace

@@ -31,9 +31,10 @@ struct Problem {
     const uint32_t* perm;   // work order: tile position -> visibility index; nullptr = identity
     int64_t cells_per_sub;  // n_v * n_u * n_w
     int32_t n_v, n_u, n_w;
-    int32_t log2_os_uv, log2_os_w;
+    int32_t log2_os_uv, log2_os_w;   // log2 of the oversampling, or -1 if not a power of two
     uint32_t guv_bytes;     // size of G_uv in bytes
     uint32_t sub_bytes;     // size of one subgrid in bytes (grid dtype)
+    int32_t os_uv, os_w;    // oversampling factors
     int32_t pad_;
     double hi_u, hi_v, hi_w;  // exclusive upper bounds of in-range coordinates
 };
@@ -97,6 +98,9 @@ hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int
 hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant, int blocks,
                                hipStream_t stream);
 hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t stream);
+// Index of the degrid kernel variant for subgrids deeper than the w support
+// (no staging; one load per w value).
+constexpr int kDeepVariant = 5;
 // *loss = sum of tile_loss[0 .. n_tiles) in a fixed order (same bits every time).
 hipError_t launch_loss_sum(const double* tile_loss, int64_t n_tiles, double* loss, hipStream_t stream);
 // *p = v (one float64 written by a kernel, so that graphs may capture it).

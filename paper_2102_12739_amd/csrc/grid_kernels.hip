@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParam
 
         bool staged = false;
         int bx0 = 0, by0 = 0, bw = 0, bh = 0, bp = 0;
-        if constexpr (BOX > 0) {
+        if (BOX > 0 && pr.n_w == kSupportW) {   // the box holds w 0..3 of each cell
             bx0 = uniform(wave_min(in_range ? x0 : 0x7FFFFFFF));
             by0 = uniform(wave_min(in_range ? y0 : 0x7FFFFFFF));
             const int bx1 = uniform(wave_max(in_range ? x0 : -1));
@@ -415,6 +415,7 @@ hipError_t launch_adjoint_v(const LaunchParams& p, int variant, int blocks, hipS
         case 2: return launch_adjoint_t<F, 2>(p, blocks, s);
         case 3: return launch_adjoint_t<F, 3>(p, blocks, s);
         case 4: return launch_adjoint_t<F, 4>(p, blocks, s);
+        case 5: return launch_adjoint_t<F, 5>(p, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -427,6 +428,7 @@ hipError_t occ_adjoint_v(int variant, int* n) {
         case 2: return occ_adjoint_t<F, 2>(n);
         case 3: return occ_adjoint_t<F, 3>(n);
         case 4: return occ_adjoint_t<F, 4>(n);
+        case 5: return occ_adjoint_t<F, 5>(n);
         default: return hipErrorInvalidValue;
     }
 }

@@ -83,9 +83,9 @@ def _desc(dg, **kw):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(os_uv=12), 1), (dict(os_w=0), 1), (dict(os_uv=128), 1), (dict(flags=1), 1),
+    (dict(os_uv=65), 1), (dict(os_w=0), 1), (dict(os_uv=128), 1), (dict(os_w=65), 1), (dict(flags=1), 1),
     (dict(n_b=65), 1), (dict(n_b=-1), 1), (dict(grid_dtype=3), 1), (dict(gcf_dtype=2), 1),
-    (dict(n_v=7), 1), (dict(support_uv=6), 2), (dict(support_w=6), 2), (dict(n_w=8), 2),
+    (dict(n_v=7), 1), (dict(support_uv=6), 2), (dict(support_w=6), 2), (dict(n_w=3), 1),
     (dict(support_uv=0), 1), (dict(n_v=8192, n_u=8192), 2),
 ])
 def test_invalid_descriptors_are_rejected_before_device_work(dg, kw, status):
@@ -126,7 +126,7 @@ def test_plan_without_device_reports_hip_error(dg):
 
 def test_python_plan_raises_degrid_error(dg):
     with pytest.raises(dg.DegridError) as e:
-        dg.Plan([0, 10], os_uv=12)
+        dg.Plan([0, 10], os_uv=65)
     assert e.value.status == 1
 
 

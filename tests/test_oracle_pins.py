@@ -176,6 +176,40 @@ def test_p3_tent_tables_equal_scipy_trilinear(oracle_mod, os_uv, os_w, n_w):
     np.testing.assert_allclose(vis, expect, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("os_uv,os_w,n_w", [(3, 5, 4), (12, 3, 6), (10, 7, 9)])
+def test_p3_tent_tables_non_power_of_two_oversampling(oracle_mod, os_uv, os_w, n_w):
+    """With an oversampling that is not a power of two, the quantised position
+    is floor(c * os) of the float64 product, over os (the rounding contract
+    of the coordinate stage); tent tables make degridding trilinear
+    interpolation at that position (scipy). Points on and one float next to
+    the lattice j / os are included, where the contract decides the cell."""
+    rng = np.random.default_rng(120 + os_uv)
+    n_v, n_u = 20, 22
+    g_uv = wl.gcf_uv(os_uv, np.float64, window=wl.tent)
+    g_w = wl.gcf_w(os_w, np.float64, window=wl.tent)
+    box = wl.interior_box(n_v, n_u, n_w)
+    uvw = wl.uniform_coords(rng, 120, box)
+    edge = []
+    for _ in range(40):
+        j = [int(rng.integers(int(np.ceil(lo * os)), int(np.floor(hi * os))))
+             for lo, hi, os in zip(box.lo, box.hi, (os_uv, os_uv, os_w))]
+        c = np.array([j[0] / os_uv, j[1] / os_uv, j[2] / os_w])
+        for step in (None, -np.inf, np.inf):
+            e = c if step is None else np.nextafter(c, step)
+            if np.all(e >= box.lo) and np.all(e < box.hi):
+                edge.append(e)
+    uvw = np.concatenate([uvw, np.array(edge)])
+    n = len(uvw)
+    a = rng.standard_normal((1, n_v, n_u, n_w)) + 1j * rng.standard_normal((1, n_v, n_u, n_w))
+    vis, oob = oracle_mod.degrid(a, g_uv, g_w, uvw, [0, n])
+    assert oob == 0
+    q = np.array([[math.floor(c * os) / os for c, os in zip(row, (os_uv, os_uv, os_w))] for row in uvw])
+    coords = np.stack([q[:, 1], q[:, 0], q[:, 2]])
+    expect = (ndi.map_coordinates(a[0].real, coords, order=1, mode="constant") +
+              1j * ndi.map_coordinates(a[0].imag, coords, order=1, mode="constant"))
+    np.testing.assert_allclose(vis, expect, rtol=0, atol=1e-12)
+
+
 def test_p3_off_lattice_coordinates_quantise_down(oracle_mod):
     """Off-lattice points interpolate at floor(c*os)/os (exact rational floor)."""
     rng = np.random.default_rng(106)
