@@ -29,6 +29,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_VIS = {"c64": 2048 + 256 + 16 + 24 + 8, "cbf16": 1024 + 128 + 8 + 24 + 8, "cf16": 1024 + 128 + 8 + 24 + 8}
+# 16-bit forms of the same inputs: (storage, tables). fp16/fp16 and bf16/bf16
+# take the packed 16-bit dot products for the w sums; bf16 storage with fp16
+# tables widens both to float32.
+LOW_PRECISION_FORMS = (("cbf16", "f16"), ("cf16", "f16"), ("cbf16", "bf16"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "degrid_fp32_paper_scale_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_12739_amd", "csrc", f)
                   for f in ("degrid_kernels.hip", "dg_device.h", "dg_internal.h")]
@@ -72,9 +76,12 @@ def upload_inputs(p, grid_dtype="c64", gcf_dtype="f32"):
         sub = torch.from_numpy(wl.complex_to_storage(p.subgrids, "cbf16").view(np.int16)).to(dev).view(torch.bfloat16)
     else:
         sub = torch.from_numpy(wl.complex_to_storage(p.subgrids, "cf16")).to(dev)
-    gdt = np.float32 if gcf_dtype == "f32" else np.float16
-    return (sub, torch.from_numpy(p.g_uv.astype(gdt)).to(dev), torch.from_numpy(p.g_w.astype(gdt)).to(dev),
-            torch.from_numpy(p.uvw).to(dev))
+    def table(t):
+        st = wl.table_to_storage(t, gcf_dtype)
+        if gcf_dtype == "bf16":
+            return torch.from_numpy(st.view(np.int16)).to(dev).view(torch.bfloat16)
+        return torch.from_numpy(st).to(dev)
+    return sub, table(p.g_uv), table(p.g_w), torch.from_numpy(p.uvw).to(dev)
 
 
 def time_plan(plan, inputs, out, steps, warmup):
@@ -310,22 +317,24 @@ def main(argv=None):
                                  "achieved_gbs": bytes_launch / (kms_in_order * 1e-3) / 1e9}
 
     # Low-precision storage of the same inputs (complex bf16 / fp16 subgrids,
-    # fp16 tables, fp32 accumulation).
+    # fp16 / bf16 tables, fp32 accumulation), each with the plan's default kernel.
     variants = {}
     if not args.no_variants:
-        for gdt in ("cbf16", "cf16"):
-            vin = upload_inputs(p, gdt, "f16")
-            vplan = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w, grid_dtype=gdt, gcf_dtype="f16")
+        for gdt, tdt in LOW_PRECISION_FORMS:
+            key = f"{gdt}/{tdt}"
+            vin = upload_inputs(p, gdt, tdt)
+            vplan = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w, grid_dtype=gdt, gcf_dtype=tdt)
             if not args.input_order:
                 vplan.sort(vin[3])
             vout = torch.empty_like(out)
             vms, vkms = time_plan(vplan, vin, vout, args.steps, args.warmup)
-            variants[gdt] = {"value": p.n_vis / (vms * 1e-3), "ms_per_step": vms, "kernel_ms": vkms,
-                             "speedup_vs_fp32": ms_step / vms,
+            variants[key] = {"value": p.n_vis / (vms * 1e-3), "ms_per_step": vms, "kernel_ms": vkms,
+                             "speedup_vs_fp32": ms_step / vms, "grid_dtype": gdt, "gcf_dtype": tdt,
+                             "kernel": vplan.info()["kernel"],
                              "achieved_gbs": BYTES_PER_VIS[gdt] * p.n_vis / (vkms * 1e-3) / 1e9,
                              "out": vout}
             del vin
-            log(f"{gdt}: {vms:.4f} ms/step ({variants[gdt]['speedup_vs_fp32']:.2f}x fp32)")
+            log(f"{key}: {vms:.4f} ms/step ({variants[key]['speedup_vs_fp32']:.2f}x fp32)")
 
     if not args.no_cpu_baseline:
         import oracle
@@ -356,9 +365,11 @@ def main(argv=None):
                                   "host_cores": cores, "cpu_model": cpu_model()}
         result["rel_l2"] = rel
         result["max_abs"] = float(np.max(np.abs(got - ref)))
-        for gdt, v in variants.items():
+        for v in variants.values():
+            gdt, tdt = v["grid_dtype"], v["gcf_dtype"]
             deq = wl.storage_to_complex128(wl.complex_to_storage(p.subgrids, gdt), gdt)
-            ref_q, _ = oracle.degrid(deq, p.g_uv.astype(np.float16), p.g_w.astype(np.float16), p.uvw, p.offsets)
+            g_uv_q, g_w_q = wl.stored_tables(p, tdt)
+            ref_q, _ = oracle.degrid(deq, g_uv_q, g_w_q, p.uvw, p.offsets)
             gv = v["out"].cpu().numpy().astype(np.complex128)
             v["rel_l2_vs_fp32_inputs"] = float(np.linalg.norm(gv - ref) / np.linalg.norm(ref))
             v["rel_l2_vs_stored_inputs"] = float(np.linalg.norm(gv - ref_q) / np.linalg.norm(ref_q))
@@ -434,61 +445,71 @@ def bench_batched(steps, warmup, check):
     del ins, batch, plans
     torch.cuda.empty_cache()
 
-    # The same eight problems with complex bf16 subgrids and fp16 tables
-    # (fp32 accumulation, fp64 index arithmetic), one graph launch.
-    bins = [upload_inputs(p, "cbf16", "f16") for p in probs]
-    bplans = []
-    for p, i in zip(probs, bins):
-        pl = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w, grid_dtype="cbf16", gcf_dtype="f16")
-        pl.sort(i[3])
-        bplans.append(pl)
-    t = time.perf_counter()
-    bkernel, bn_b = batch_tune(bplans, bins, outs=outs)
-    btune_s = time.perf_counter() - t
-    bbatch = Batch(bplans)
+    # The same eight problems in 16-bit forms, one graph launch each: bf16
+    # storage with bf16 tables (the bf16 form; packed bf16 dot products) and
+    # fp16 storage with fp16 tables (packed fp16 dot products); fp32
+    # accumulation and fp64 index arithmetic in both.
+    low_out = {}
+    for key, gdt, tdt in (("batch_graph_bf16", "cbf16", "bf16"), ("batch_graph_fp16", "cf16", "f16")):
+        lins = [upload_inputs(p, gdt, tdt) for p in probs]
+        lplans = []
+        for p, i in zip(probs, lins):
+            pl = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w, grid_dtype=gdt, gcf_dtype=tdt)
+            pl.sort(i[3])
+            lplans.append(pl)
+        t = time.perf_counter()
+        lkernel, ln_b = batch_tune(lplans, lins, outs=outs)
+        ltune_s = time.perf_counter() - t
+        lbatch = Batch(lplans)
 
-    def run_bf16():
-        bbatch.execute(bins, outs=outs, stream=stream)
+        def run_low():
+            lbatch.execute(lins, outs=outs, stream=stream)
 
-    for _ in range(warmup):
-        run_bf16()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        run_bf16()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    res["batch_graph_bf16"] = {"ms_per_step": ms, "value": n_vis / (ms * 1e-3),
-                               "grid_dtype": "cbf16", "gcf_dtype": "f16",
-                               "autotune": {"kernel": bkernel, "n_b": bn_b, "tune_s": btune_s},
-                               "speedup_vs_plain_fp32_separate": res["separate_launches"]["ms_per_step"] / ms,
-                               "speedup_vs_batch_fp32": res["batch_graph"]["ms_per_step"] / ms,
-                               "achieved_gbs": BYTES_PER_VIS["cbf16"] * n_vis / (ms * 1e-3) / 1e9}
-    run_bf16()
-    torch.cuda.synchronize()
-    bf16_out = [o.cpu().numpy().astype(np.complex128) for o in outs]
-    bbatch.close()
+        for _ in range(warmup):
+            run_low()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run_low()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[key] = {"ms_per_step": ms, "value": n_vis / (ms * 1e-3), "grid_dtype": gdt, "gcf_dtype": tdt,
+                    "autotune": {"kernel": lkernel, "n_b": ln_b, "tune_s": ltune_s},
+                    "speedup_vs_plain_fp32_separate": res["separate_launches"]["ms_per_step"] / ms,
+                    "speedup_vs_batch_fp32": res["batch_graph"]["ms_per_step"] / ms,
+                    "achieved_gbs": BYTES_PER_VIS[gdt] * n_vis / (ms * 1e-3) / 1e9}
+        run_low()
+        torch.cuda.synchronize()
+        low_out[key] = [o.cpu().numpy().astype(np.complex128) for o in outs]
+        lbatch.close()
+        del lins, lbatch, lplans
+        torch.cuda.empty_cache()
     if check:
         import oracle
-        acc = {"fp32": [0.0, 0.0], "bf16_vs_fp32_inputs": [0.0, 0.0], "bf16_vs_stored_inputs": [0.0, 0.0]}
-        worst = 0.0
-        for p, g32, g16 in zip(probs, fp32_out, bf16_out):
+        acc = {"fp32": [0.0, 0.0]}
+        worst = {k: 0.0 for k in low_out}
+        for j, p in enumerate(probs):
             ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
-            deq = wl.storage_to_complex128(wl.complex_to_storage(p.subgrids, "cbf16"), "cbf16")
-            ref_q, _ = oracle.degrid(deq, p.g_uv.astype(np.float16), p.g_w.astype(np.float16), p.uvw, p.offsets)
-            for key, got, r in (("fp32", g32, ref), ("bf16_vs_fp32_inputs", g16, ref),
-                                ("bf16_vs_stored_inputs", g16, ref_q)):
-                acc[key][0] += float(np.sum(np.abs(got - r) ** 2))
-                acc[key][1] += float(np.sum(np.abs(r) ** 2))
-            worst = max(worst, float(np.max(np.abs(g16 - ref))))
+            pairs = [("fp32", fp32_out[j], ref)]
+            for key, lo in low_out.items():
+                gdt, tdt = res[key]["grid_dtype"], res[key]["gcf_dtype"]
+                deq = wl.storage_to_complex128(wl.complex_to_storage(p.subgrids, gdt), gdt)
+                g_uv_q, g_w_q = wl.stored_tables(p, tdt)
+                ref_q, _ = oracle.degrid(deq, g_uv_q, g_w_q, p.uvw, p.offsets)
+                pairs += [(key + ":fp32_inputs", lo[j], ref), (key + ":stored_inputs", lo[j], ref_q)]
+                worst[key] = max(worst[key], float(np.max(np.abs(lo[j] - ref))))
+            for name, got, r in pairs:
+                a = acc.setdefault(name, [0.0, 0.0])
+                a[0] += float(np.sum(np.abs(got - r) ** 2))
+                a[1] += float(np.sum(np.abs(r) ** 2))
         res["rel_l2"] = (acc["fp32"][0] / acc["fp32"][1]) ** 0.5
-        res["batch_graph_bf16"]["rel_l2_vs_fp32_inputs"] = (acc["bf16_vs_fp32_inputs"][0] /
-                                                            acc["bf16_vs_fp32_inputs"][1]) ** 0.5
-        res["batch_graph_bf16"]["rel_l2_vs_stored_inputs"] = (acc["bf16_vs_stored_inputs"][0] /
-                                                              acc["bf16_vs_stored_inputs"][1]) ** 0.5
-        res["batch_graph_bf16"]["max_abs_vs_fp32_inputs"] = worst
+        for key in low_out:
+            for which in ("fp32_inputs", "stored_inputs"):
+                a = acc[f"{key}:{which}"]
+                res[key][f"rel_l2_vs_{which}"] = (a[0] / a[1]) ** 0.5
+            res[key]["max_abs_vs_fp32_inputs"] = worst[key]
     log(f"batched: graph {res['batch_graph']['ms_per_step']:.3f} ms, separate {res['separate_launches']['ms_per_step']:.3f} ms, "
-        f"bf16 graph {res['batch_graph_bf16']['ms_per_step']:.3f} ms")
+        f"bf16 graph {res['batch_graph_bf16']['ms_per_step']:.3f} ms, fp16 graph {res['batch_graph_fp16']['ms_per_step']:.3f} ms")
     return res
 
 

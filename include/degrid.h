@@ -74,10 +74,14 @@ typedef enum {
     DG_GRID_CF16 = 2   /* complex float16 (re, im), 4 bytes per value   */
 } dg_grid_dtype;
 
-/* Storage type of the G_uv and G_w tables. */
+/* Storage type of the G_uv and G_w tables. Any table type goes with any
+ * storage type. With DG_GRID_CF16 storage and DG_GCF_F16 tables, or
+ * DG_GRID_CBF16 and DG_GCF_BF16, the sums over w run on the packed 16-bit dot
+ * products (each product exact in float32, float32 accumulation). */
 typedef enum {
     DG_GCF_F32 = 0,
-    DG_GCF_F16 = 1
+    DG_GCF_F16 = 1,
+    DG_GCF_BF16 = 2
 } dg_gcf_dtype;
 
 /* Problem descriptor (Section 2: subgrid size, GCF supports and oversampling). */
@@ -137,6 +141,11 @@ dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_o
  *   vis_out   device complex float32 [N]; every entry is written.
  * Asynchronous on 'stream'; allocates nothing. The out-of-range count of this
  * call replaces the plan's previous count.
+ * Alignment (every entry point that takes these arrays): each element
+ * naturally aligned (subgrids 8 bytes for complex float32, 4 for the 16-bit
+ * complex types; g_uv 4 or 2; uvw and complex float32 arrays 8), and g_w on
+ * a 4-byte boundary whatever its dtype (its rows are read as whole 32-bit
+ * words). A misaligned pointer gives DG_ERR_INVALID_ARG and launches nothing.
  */
 dg_status degrid_execute(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w,
                          const double* uvw, void* vis_out, hipStream_t stream);

@@ -68,7 +68,7 @@ dg_status validate_desc(const dg_desc* d) {
         return fail(DG_ERR_INVALID_ARG, "oversampling must be in [1, 64], got %d and %d", d->os_uv, d->os_w);
     if (d->grid_dtype < DG_GRID_C64 || d->grid_dtype > DG_GRID_CF16)
         return fail(DG_ERR_INVALID_ARG, "unknown grid dtype %d", d->grid_dtype);
-    if (d->gcf_dtype < DG_GCF_F32 || d->gcf_dtype > DG_GCF_F16)
+    if (d->gcf_dtype < DG_GCF_F32 || d->gcf_dtype > DG_GCF_BF16)
         return fail(DG_ERR_INVALID_ARG, "unknown gcf dtype %d", d->gcf_dtype);
     if (d->n_b < 0 || d->n_b > kMaxNb)
         return fail(DG_ERR_INVALID_ARG, "n_b must be in [0, %d], got %d", kMaxNb, d->n_b);
@@ -228,6 +228,31 @@ struct dg_batch_ {
 
 namespace {
 
+// Alignment of the device pointers: every element naturally aligned, and
+// the G_w table on a 4-byte boundary, because its rows are read as whole
+// dwords through the scalar cache. Null pointers are not checked here.
+dg_status check_alignment(const dg_desc& d, const void* subgrids, const void* g_uv, const void* g_w,
+                          const void* uvw, const void* vis, const void* v_obs, const void* grid_out) {
+    struct Need {
+        const void* ptr;
+        uintptr_t align;
+        const char* name;
+    };
+    const Need need[] = {
+        {subgrids, grid_elem_bytes(d.grid_dtype), "subgrids"},
+        {g_uv, gcf_elem_bytes(d.gcf_dtype), "g_uv"},
+        {g_w, 4, "g_w"},
+        {uvw, 8, "uvw"},
+        {vis, 8, "the visibility array"},
+        {v_obs, 8, "v_obs"},
+        {grid_out, 8, "subgrids_out"},
+    };
+    for (const Need& n : need)
+        if (n.ptr && reinterpret_cast<uintptr_t>(n.ptr) % n.align != 0)
+            return fail(DG_ERR_INVALID_ARG, "%s must be %u-byte aligned", n.name, (unsigned)n.align);
+    return DG_OK;
+}
+
 Problem problem_of(const dg_plan_* p, const void* subgrids, const void* g_uv, const void* g_w,
                    const double* uvw, void* vis, void* grid_out) {
     const dg_desc& d = p->desc;
@@ -327,9 +352,11 @@ void tune_cache_store(const std::string& key, int32_t n_b, int32_t variant) {
 }
 
 // Default tile size and kernel variant when neither the caller nor the tuning
-// cache fixes them.
+// cache fixes them: complex float32 stages tiles in 16 KiB LDS boxes; the
+// 16-bit storage types gather through the caches (their cells are half as
+// wide, and the staging copy costs more than it saves).
 constexpr int32_t kDefaultNb = 64;
-constexpr int32_t kDefaultVariant = 4;
+int32_t default_variant(const dg_desc& d) { return d.grid_dtype == DG_GRID_C64 ? 4 : 0; }
 
 // Subgrids with more w planes than the w support have taps that start at any
 // w: only the deep variant (no staging, one load per w value) reads them.
@@ -447,7 +474,7 @@ dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_o
     p->desc = *d;
     p->n_sub = n_subgrids;
     p->offsets.assign(vis_offsets, vis_offsets + n_subgrids + 1);
-    int32_t n_b = d->n_b, variant = kDefaultVariant;
+    int32_t n_b = d->n_b, variant = default_variant(*d);
     if (n_b == 0 && !tune_cache_lookup(tune_key(p), &n_b, &variant)) n_b = kDefaultNb;
     if (!variant_allowed(*d, variant)) variant = kDeepVariant;
     p->variant = variant;
@@ -469,6 +496,8 @@ dg_status degrid_execute(dg_plan p, const void* subgrids, const void* g_uv, cons
     if (p->ds.n_tiles == 0) return DG_OK;   // no visibilities: nothing to write
     if (!subgrids || !g_uv || !g_w || !uvw || !vis_out)
         return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+    if (dg_status s = check_alignment(p->desc, subgrids, g_uv, g_w, uvw, vis_out, nullptr, nullptr); s != DG_OK)
+        return s;
     const Problem pr = problem_of(p, subgrids, g_uv, g_w, uvw, vis_out, nullptr);
     hipError_t e = launch_degrid(params_for(p, pr), p->desc.grid_dtype, p->desc.gcf_dtype, p->variant,
                                  p->blocks, stream);
@@ -489,6 +518,8 @@ dg_status degrid_residual(dg_plan p, const void* subgrids, const void* g_uv, con
     }
     if (!subgrids || !g_uv || !g_w || !uvw || !v_obs || !res_out)
         return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+    if (dg_status s = check_alignment(p->desc, subgrids, g_uv, g_w, uvw, res_out, v_obs, nullptr); s != DG_OK)
+        return s;
     const Problem pr = problem_of(p, subgrids, g_uv, g_w, uvw, res_out, nullptr);
     LaunchParams lp = params_for(p, pr);
     lp.v_obs = static_cast<const float2*>(v_obs);
@@ -510,6 +541,8 @@ dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void*
     if (p->d_own_blocks && p->offsets.back() > 0) {
         // owner-computes: every output block written once, then the fix-up
         if (!vis || !g_uv || !g_w || !uvw) return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+        if (dg_status s = check_alignment(p->desc, nullptr, g_uv, g_w, uvw, vis, nullptr, subgrids_out); s != DG_OK)
+            return s;
         OwnerParams op{};
         op.prob = problem_of(p, nullptr, g_uv, g_w, uvw, const_cast<void*>(vis), subgrids_out);
         op.blocks = p->d_own_blocks;
@@ -529,6 +562,8 @@ dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void*
         p->launched = true;
         return DG_OK;
     }
+    if (dg_status s = check_alignment(p->desc, nullptr, g_uv, g_w, uvw, vis, nullptr, subgrids_out); s != DG_OK)
+        return s;
     if (!accumulate) {
         hipError_t e = launch_zero(subgrids_out, out_bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "zero-fill kernel launch");
@@ -577,6 +612,8 @@ dg_status degrid_tune(dg_plan p, const void* subgrids, const void* g_uv, const v
     if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");
     if (!subgrids || !g_uv || !g_w || !uvw || !vis_out)
         return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+    if (dg_status s = check_alignment(p->desc, subgrids, g_uv, g_w, uvw, vis_out, nullptr, nullptr); s != DG_OK)
+        return s;
     if (p->offsets.back() == 0) return DG_OK;
     static const int32_t kCandidates[] = {8, 16, 32, 64};
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -788,6 +825,9 @@ dg_status degrid_batch_execute(dg_batch b, const void* const* args, hipStream_t 
         if (b->plans[i]->offsets.back() == 0) continue;
         for (int k = 0; k < 5; ++k)
             if (!args[5 * i + k]) return fail(DG_ERR_INVALID_ARG, "args[%zu] is NULL", 5 * i + k);
+        const void* const* a = args + 5 * i;
+        if (dg_status s = check_alignment(b->plans[i]->desc, a[0], a[1], a[2], a[3], a[4], nullptr, nullptr); s != DG_OK)
+            return s;
     }
     for (size_t i = 0; i < n; ++i)
         if (b->plans[i]->version != b->plan_versions[i])

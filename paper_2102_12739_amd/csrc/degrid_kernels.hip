@@ -58,20 +58,33 @@ __device__ __forceinline__ void fetch8(Fetch8<G>& f, int g0, int a_off, __amdgpu
 }
 
 // Weighted sums of visibilities g0 .. g0+7 from their fetched values; gv[k]
-// is this lane's G_uv weight of visibility g0 + k, and the G_w rows come
-// through the scalar cache. Results land in out[g0 .. g0+7].
+// is this lane's G_uv weight of visibility g0 + k, and the G_w rows (lane j
+// holds the byte offset gw_off of visibility j's row) come through the
+// scalar cache. Results land in out[g0 .. g0+7].
 template <int G, int F>
-__device__ __forceinline__ void sum8(const Fetch8<G>& f, const float* gv, int ow, uint64_t g_w, float2* out,
-                                     int g0) {
+__device__ __forceinline__ void sum8(const Fetch8<G>& f, const float* gv, uint32_t gw_off, uint64_t g_w,
+                                     float2* out, int g0) {
     const int lane = lane_id();
     float pre[8], pim[8];
+    uint2 gwp[8];
+    if constexpr (kPackedDot<G, F>) {
+        // the eight rows' scalar loads go out together, ahead of the sums
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            gwp[k] = load_gw_pairs(g_w, (uint32_t)__builtin_amdgcn_readlane((int)gw_off, g0 + k));
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const float4 gw = load_gw_row<F>(g_w, __builtin_amdgcn_readlane(ow, g0 + k));
-        float re[4], im[4];
-        widen_w4<G>(f.raw[k], re, im);
-        const float sr = gw.x * re[0] + gw.y * re[1] + gw.z * re[2] + gw.w * re[3];
-        const float si = gw.x * im[0] + gw.y * im[1] + gw.z * im[2] + gw.w * im[3];
+        float sr, si;
+        if constexpr (kPackedDot<G, F>) {
+            wsum_packed<G>(f.raw[k], gwp[k], sr, si);
+        } else {
+            const float4 gw = load_gw_row<F>(g_w, (uint32_t)__builtin_amdgcn_readlane((int)gw_off, g0 + k));
+            float re[4], im[4];
+            widen_w4<G>(f.raw[k], re, im);
+            sr = gw.x * re[0] + gw.y * re[1] + gw.z * re[2] + gw.w * re[3];
+            si = gw.x * im[0] + gw.y * im[1] + gw.z * im[2] + gw.w * im[3];
+        }
         pre[k] = gv[k] * sr;
         pim[k] = gv[k] * si;
     }
@@ -85,6 +98,7 @@ template <int G, int F, int NB, bool STAGED, uint32_t PLANE1, bool DEEP>
 __device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, int ow, const float* gv,
                                             __amdgpu_buffer_rsrc_t ra, uint64_t g_w, uint32_t lane_a,
                                             const char* box) {
+    const uint32_t gw_off = gw_row_offset<F>(ow);
     Fetch8<G> buf[2];
     fetch8<G, STAGED, PLANE1, DEEP>(buf[0], 0, a_off, ra, lane_a, box);
 #pragma unroll
@@ -92,7 +106,7 @@ __device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, i
         if (g0 < count) {
             if (g0 + 8 < NB && g0 + 8 < count)
                 fetch8<G, STAGED, PLANE1, DEEP>(buf[((g0 / 8) + 1) & 1], g0 + 8, a_off, ra, lane_a, box);
-            sum8<G, F>(buf[(g0 / 8) & 1], gv + g0, ow, g_w, out, g0);
+            sum8<G, F>(buf[(g0 / 8) & 1], gv + g0, gw_off, g_w, out, g0);
         }
     }
 }
@@ -426,25 +440,31 @@ int degrid_variant_max_nb(int variant) {
 
 hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int variant,
                          int blocks, hipStream_t stream) {
-    switch (grid_kind * 2 + gcf_kind) {
-        case kGridC64 * 2 + kGcfF32: return launch_degrid_v<kGridC64, kGcfF32>(p, variant, blocks, stream);
-        case kGridC64 * 2 + kGcfF16: return launch_degrid_v<kGridC64, kGcfF16>(p, variant, blocks, stream);
-        case kGridCBF16 * 2 + kGcfF32: return launch_degrid_v<kGridCBF16, kGcfF32>(p, variant, blocks, stream);
-        case kGridCBF16 * 2 + kGcfF16: return launch_degrid_v<kGridCBF16, kGcfF16>(p, variant, blocks, stream);
-        case kGridCF16 * 2 + kGcfF32: return launch_degrid_v<kGridCF16, kGcfF32>(p, variant, blocks, stream);
-        case kGridCF16 * 2 + kGcfF16: return launch_degrid_v<kGridCF16, kGcfF16>(p, variant, blocks, stream);
+    switch (grid_kind * 3 + gcf_kind) {
+        case kGridC64 * 3 + kGcfF32: return launch_degrid_v<kGridC64, kGcfF32>(p, variant, blocks, stream);
+        case kGridC64 * 3 + kGcfF16: return launch_degrid_v<kGridC64, kGcfF16>(p, variant, blocks, stream);
+        case kGridC64 * 3 + kGcfBF16: return launch_degrid_v<kGridC64, kGcfBF16>(p, variant, blocks, stream);
+        case kGridCBF16 * 3 + kGcfF32: return launch_degrid_v<kGridCBF16, kGcfF32>(p, variant, blocks, stream);
+        case kGridCBF16 * 3 + kGcfF16: return launch_degrid_v<kGridCBF16, kGcfF16>(p, variant, blocks, stream);
+        case kGridCBF16 * 3 + kGcfBF16: return launch_degrid_v<kGridCBF16, kGcfBF16>(p, variant, blocks, stream);
+        case kGridCF16 * 3 + kGcfF32: return launch_degrid_v<kGridCF16, kGcfF32>(p, variant, blocks, stream);
+        case kGridCF16 * 3 + kGcfF16: return launch_degrid_v<kGridCF16, kGcfF16>(p, variant, blocks, stream);
+        case kGridCF16 * 3 + kGcfBF16: return launch_degrid_v<kGridCF16, kGcfBF16>(p, variant, blocks, stream);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t degrid_kernel_occupancy(int grid_kind, int gcf_kind, int variant, int* n) {
-    switch (grid_kind * 2 + gcf_kind) {
-        case kGridC64 * 2 + kGcfF32: return occ_degrid_v<kGridC64, kGcfF32>(variant, n);
-        case kGridC64 * 2 + kGcfF16: return occ_degrid_v<kGridC64, kGcfF16>(variant, n);
-        case kGridCBF16 * 2 + kGcfF32: return occ_degrid_v<kGridCBF16, kGcfF32>(variant, n);
-        case kGridCBF16 * 2 + kGcfF16: return occ_degrid_v<kGridCBF16, kGcfF16>(variant, n);
-        case kGridCF16 * 2 + kGcfF32: return occ_degrid_v<kGridCF16, kGcfF32>(variant, n);
-        case kGridCF16 * 2 + kGcfF16: return occ_degrid_v<kGridCF16, kGcfF16>(variant, n);
+    switch (grid_kind * 3 + gcf_kind) {
+        case kGridC64 * 3 + kGcfF32: return occ_degrid_v<kGridC64, kGcfF32>(variant, n);
+        case kGridC64 * 3 + kGcfF16: return occ_degrid_v<kGridC64, kGcfF16>(variant, n);
+        case kGridC64 * 3 + kGcfBF16: return occ_degrid_v<kGridC64, kGcfBF16>(variant, n);
+        case kGridCBF16 * 3 + kGcfF32: return occ_degrid_v<kGridCBF16, kGcfF32>(variant, n);
+        case kGridCBF16 * 3 + kGcfF16: return occ_degrid_v<kGridCBF16, kGcfF16>(variant, n);
+        case kGridCBF16 * 3 + kGcfBF16: return occ_degrid_v<kGridCBF16, kGcfBF16>(variant, n);
+        case kGridCF16 * 3 + kGcfF32: return occ_degrid_v<kGridCF16, kGcfF32>(variant, n);
+        case kGridCF16 * 3 + kGcfF16: return occ_degrid_v<kGridCF16, kGcfF16>(variant, n);
+        case kGridCF16 * 3 + kGcfBF16: return occ_degrid_v<kGridCF16, kGcfBF16>(variant, n);
         default: return hipErrorInvalidValue;
     }
 }

@@ -201,14 +201,21 @@ __device__ __forceinline__ void widen_w4(const uint32_t (&raw)[GridTraits<G>::kW
 template <int F> struct GcfTraits;
 template <> struct GcfTraits<kGcfF32> { static constexpr uint32_t kBytes = 4; };
 template <> struct GcfTraits<kGcfF16> { static constexpr uint32_t kBytes = 2; };
+template <> struct GcfTraits<kGcfBF16> { static constexpr uint32_t kBytes = 2; };
+
+// One 16-bit table value (the low half of h) widened to float32.
+template <int F>
+__device__ __forceinline__ float widen_gcf16(uint32_t h) {
+    if constexpr (F == kGcfBF16) return __uint_as_float(h << 16);
+    else return __half2float(__builtin_bit_cast(__half, (unsigned short)h));
+}
 
 template <int F>
 __device__ __forceinline__ float load_gcf_rsrc(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     if constexpr (F == kGcfF32) {
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
     } else {
-        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
-        return __half2float(__builtin_bit_cast(__half, h));
+        return widen_gcf16<F>(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
     }
 }
 
@@ -217,7 +224,7 @@ __device__ __forceinline__ float load_gcf(const void* table, int64_t idx) {
     if constexpr (F == kGcfF32) {
         return static_cast<const float*>(table)[idx];
     } else {
-        return __half2float(static_cast<const __half*>(table)[idx]);
+        return widen_gcf16<F>(static_cast<const unsigned short*>(table)[idx]);
     }
 }
 
@@ -338,6 +345,8 @@ __device__ __forceinline__ int wave_max(int x) {
 // address become scalar loads.
 typedef const __attribute__((address_space(4))) float* ConstF32Ptr;
 typedef const __attribute__((address_space(4))) uint32_t* ConstU32Ptr;
+typedef uint32_t U32x2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(4))) U32x2* ConstU32x2Ptr;
 typedef const __attribute__((address_space(4))) Tile* ConstTilePtr;
 typedef const __attribute__((address_space(4))) Problem* ConstProblemPtr;
 
@@ -388,17 +397,81 @@ __device__ __forceinline__ const double* problem_uvw(const LaunchParams& P, int 
     return p->uvw;
 }
 
-// G_w[o_w][0..3] as four floats, read through the scalar cache.
+// Byte offset of G_w row o_w in a table of type F.
 template <int F>
-__device__ __forceinline__ float4 load_gw_row(uint64_t g_w, int ow) {
+__device__ __forceinline__ uint32_t gw_row_offset(int ow) {
+    return (uint32_t)ow * (GcfTraits<F>::kBytes * kSupportW);
+}
+
+// G_w row of a 16-bit table at byte offset off as two packed pairs (g0, g1),
+// (g2, g3), read through the scalar cache.
+__device__ __forceinline__ uint2 load_gw_pairs(uint64_t g_w, uint32_t off) {
+    const U32x2 v = *(ConstU32x2Ptr)(g_w + off);
+    return make_uint2(v.x, v.y);
+}
+
+// Storage and table types whose w sums run on the packed 16-bit dot products
+// (v_dot2_f32_f16, v_dot2_f32_bf16): storage and G_w of the same 16-bit type.
+// Each product of two such values is exact in float32.
+template <int G, int F>
+constexpr bool kPackedDot = (G == kGridCF16 && F == kGcfF16) || (G == kGridCBF16 && F == kGcfBF16);
+
+typedef _Float16 Half2V __attribute__((ext_vector_type(2)));
+typedef __bf16 BF16x2V __attribute__((ext_vector_type(2)));
+
+// a.lo * b.lo + a.hi * b.hi + c, float32 accumulation
+template <int G>
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+    static_assert(G == kGridCF16 || G == kGridCBF16, "packed dot products cover 16-bit storage");
+    if constexpr (G == kGridCF16)
+        return __builtin_amdgcn_fdot2(__builtin_bit_cast(Half2V, a), __builtin_bit_cast(Half2V, b), c, false);
+    else
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(BF16x2V, a), __builtin_bit_cast(BF16x2V, b), c,
+                                               false);
+}
+
+// The same with c = 0. The builtin with a zero accumulator becomes a move of
+// 0 and the two-operand v_dot2c form; the three-operand form takes 0 as an
+// inline constant, which saves the move. b is wavefront-uniform (a G_w pair).
+template <int G>
+__device__ __forceinline__ float dot2_first(uint32_t a, uint32_t b) {
+    static_assert(G == kGridCF16 || G == kGridCBF16, "packed dot products cover 16-bit storage");
+    float d;
+    if constexpr (G == kGridCF16)
+        asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "s"(b), "v"(a));
+    else
+        asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(d) : "s"(b), "v"(a));
+    return d;
+}
+
+// sum_t G_w[t] * A[t] over the 4 w values of one fetched cell, for 16-bit
+// storage with a G_w table of the same type: v_perm pairs the real parts (and
+// the imaginary parts) of two adjacent w values so that one dot product
+// takes two taps.
+template <int G>
+__device__ __forceinline__ void wsum_packed(const uint32_t (&raw)[GridTraits<G>::kWords], uint2 gw, float& sr,
+                                            float& si) {
+    // v_perm_b32 selects bytes of {src0 : src1}; bytes 0-3 are src1's.
+    constexpr uint32_t kLowHalves = 0x05040100u;    // (src1.lo, src0.lo)
+    constexpr uint32_t kHighHalves = 0x07060302u;   // (src1.hi, src0.hi)
+    const uint32_t re01 = __builtin_amdgcn_perm(raw[1], raw[0], kLowHalves);
+    const uint32_t im01 = __builtin_amdgcn_perm(raw[1], raw[0], kHighHalves);
+    const uint32_t re23 = __builtin_amdgcn_perm(raw[3], raw[2], kLowHalves);
+    const uint32_t im23 = __builtin_amdgcn_perm(raw[3], raw[2], kHighHalves);
+    sr = dot2<G>(re23, gw.y, dot2_first<G>(re01, gw.x));
+    si = dot2<G>(im23, gw.y, dot2_first<G>(im01, gw.x));
+}
+
+// G_w row at byte offset off as four floats, read through the scalar cache.
+template <int F>
+__device__ __forceinline__ float4 load_gw_row(uint64_t g_w, uint32_t off) {
     if constexpr (F == kGcfF32) {
-        const ConstF32Ptr p = (ConstF32Ptr)g_w + ow * kSupportW;
+        const ConstF32Ptr p = (ConstF32Ptr)(g_w + off);
         return make_float4(p[0], p[1], p[2], p[3]);
     } else {
-        const ConstU32Ptr p = (ConstU32Ptr)g_w + ow * (kSupportW / 2);
-        const __half2 a = __builtin_bit_cast(__half2, p[0]);
-        const __half2 b = __builtin_bit_cast(__half2, p[1]);
-        return make_float4(__low2float(a), __high2float(a), __low2float(b), __high2float(b));
+        const U32x2 v = *(ConstU32x2Ptr)(g_w + off);
+        return make_float4(widen_gcf16<F>(v.x & 0xFFFFu), widen_gcf16<F>(v.x >> 16), widen_gcf16<F>(v.y & 0xFFFFu),
+                           widen_gcf16<F>(v.y >> 16));
     }
 }
 

@@ -90,7 +90,7 @@ struct OwnerParams {
 };
 
 enum GridKind : int32_t { kGridC64 = 0, kGridCBF16 = 1, kGridCF16 = 2 };
-enum GcfKind : int32_t { kGcfF32 = 0, kGcfF16 = 1 };
+enum GcfKind : int32_t { kGcfF32 = 0, kGcfF16 = 1, kGcfBF16 = 2 };
 
 // Kernel launchers (defined in degrid_kernels.hip and grid_kernels.hip).
 hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int variant,

@@ -437,12 +437,14 @@ hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant,
                                hipStream_t stream) {
     if (gcf_kind == kGcfF32) return launch_adjoint_v<kGcfF32>(p, variant, blocks, stream);
     if (gcf_kind == kGcfF16) return launch_adjoint_v<kGcfF16>(p, variant, blocks, stream);
+    if (gcf_kind == kGcfBF16) return launch_adjoint_v<kGcfBF16>(p, variant, blocks, stream);
     return hipErrorInvalidValue;
 }
 
 hipError_t adjoint_kernel_occupancy(int gcf_kind, int variant, int* n) {
     if (gcf_kind == kGcfF32) return occ_adjoint_v<kGcfF32>(variant, n);
     if (gcf_kind == kGcfF16) return occ_adjoint_v<kGcfF16>(variant, n);
+    if (gcf_kind == kGcfBF16) return occ_adjoint_v<kGcfBF16>(variant, n);
     return hipErrorInvalidValue;
 }
 
@@ -451,6 +453,8 @@ hipError_t launch_grid_owner(const OwnerParams& p, int gcf_kind, int blocks, hip
         hipLaunchKernelGGL((grid_owner_kernel<kGcfF32>), dim3(blocks), dim3(kBlockThreads), 0, stream, p);
     else if (gcf_kind == kGcfF16)
         hipLaunchKernelGGL((grid_owner_kernel<kGcfF16>), dim3(blocks), dim3(kBlockThreads), 0, stream, p);
+    else if (gcf_kind == kGcfBF16)
+        hipLaunchKernelGGL((grid_owner_kernel<kGcfBF16>), dim3(blocks), dim3(kBlockThreads), 0, stream, p);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -459,7 +463,11 @@ hipError_t launch_grid_owner(const OwnerParams& p, int gcf_kind, int blocks, hip
 hipError_t owner_kernel_occupancy(int gcf_kind, int* n) {
     if (gcf_kind == kGcfF32)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, grid_owner_kernel<kGcfF32>, kBlockThreads, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, grid_owner_kernel<kGcfF16>, kBlockThreads, 0);
+    if (gcf_kind == kGcfF16)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, grid_owner_kernel<kGcfF16>, kBlockThreads, 0);
+    if (gcf_kind == kGcfBF16)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, grid_owner_kernel<kGcfBF16>, kBlockThreads, 0);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_grid_fixup(const Problem& pr, const int64_t* vis_offsets, int64_t n_sub, int64_t n_vis,
@@ -472,6 +480,9 @@ hipError_t launch_grid_fixup(const Problem& pr, const int64_t* vis_offsets, int6
                            vis_offsets, n_sub, n_vis, plan_start, ctl);
     else if (gcf_kind == kGcfF16)
         hipLaunchKernelGGL((grid_fixup_kernel<kGcfF16>), dim3((unsigned)blocks), dim3(kBlockThreads), 0, stream, pr,
+                           vis_offsets, n_sub, n_vis, plan_start, ctl);
+    else if (gcf_kind == kGcfBF16)
+        hipLaunchKernelGGL((grid_fixup_kernel<kGcfBF16>), dim3((unsigned)blocks), dim3(kBlockThreads), 0, stream, pr,
                            vis_offsets, n_sub, n_vis, plan_start, ctl);
     else
         return hipErrorInvalidValue;

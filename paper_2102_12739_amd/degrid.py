@@ -27,7 +27,7 @@ _LIB_PATH = os.path.join(_PKG, "libdegrid.so")
 _lib = None
 
 GRID_DTYPES = {"c64": 0, "cbf16": 1, "cf16": 2}
-GCF_DTYPES = {"f32": 0, "f16": 1}
+GCF_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 _STATUS = {0: "DG_OK", 1: "DG_ERR_INVALID_ARG", 2: "DG_ERR_UNSUPPORTED", 3: "DG_ERR_NOMEM",
            4: "DG_ERR_HIP", 5: "DG_ERR_NOT_READY"}
 
@@ -133,7 +133,7 @@ def _grid_tensor_dtype(grid_dtype: str):
 
 
 def _gcf_tensor_dtype(gcf_dtype: str):
-    return {"f32": torch.float32, "f16": torch.float16}[gcf_dtype]
+    return {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[gcf_dtype]
 
 
 class Plan:

@@ -250,6 +250,35 @@ def storage_to_complex128(st: np.ndarray, grid_dtype: str) -> np.ndarray:
     return f[..., 0] + 1j * f[..., 1]
 
 
+def table_to_storage(t: np.ndarray, gcf_dtype: str) -> np.ndarray:
+    """Real GCF table -> stored form, rounded once from float32 (nearest, ties
+    to even): ``f32`` float32, ``f16`` float16, ``bf16`` uint16 bfloat16 bits."""
+    t32 = np.ascontiguousarray(t, dtype=np.float32)
+    if gcf_dtype == "f32":
+        return t32
+    if gcf_dtype == "f16":
+        return t32.astype(np.float16)
+    if gcf_dtype == "bf16":
+        return to_bf16_bits(t32)
+    raise ValueError(gcf_dtype)
+
+
+def storage_table_to_f64(st: np.ndarray, gcf_dtype: str) -> np.ndarray:
+    """Widen a stored table back to float64 (exact)."""
+    if gcf_dtype in ("f32", "f16"):
+        return st.astype(np.float64)
+    if gcf_dtype == "bf16":
+        return bf16_bits_to_f32(st).astype(np.float64)
+    raise ValueError(gcf_dtype)
+
+
+def stored_tables(p, gcf_dtype: str):
+    """(G_uv, G_w) of problem p as the library receives them in gcf_dtype,
+    widened to float64: the tables an exact reference must use."""
+    return (storage_table_to_f64(table_to_storage(p.g_uv, gcf_dtype), gcf_dtype),
+            storage_table_to_f64(table_to_storage(p.g_w, gcf_dtype), gcf_dtype))
+
+
 # ---------------------------------------------------------------------------
 # Named workloads
 # ---------------------------------------------------------------------------

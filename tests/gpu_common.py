@@ -34,11 +34,27 @@ def upload(p, grid_dtype="c64", gcf_dtype="f32"):
             out["sub"] = torch.from_numpy(st.view(np.int16)).to(dev).view(torch.bfloat16)
         else:
             out["sub"] = torch.from_numpy(st).to(dev)
-    gdt = np.float32 if gcf_dtype == "f32" else np.float16
-    out["g_uv"] = torch.from_numpy(np.ascontiguousarray(p.g_uv.astype(gdt))).to(dev)
-    out["g_w"] = torch.from_numpy(np.ascontiguousarray(p.g_w.astype(gdt))).to(dev)
+    out["g_uv"] = table_tensor(p.g_uv, gcf_dtype)
+    out["g_w"] = table_tensor(p.g_w, gcf_dtype)
     out["uvw"] = torch.from_numpy(np.ascontiguousarray(p.uvw)).to(dev)
     return out
+
+
+def table_tensor(t, gcf_dtype):
+    """A GCF table on the device in the given storage dtype."""
+    st = wl.table_to_storage(t, gcf_dtype)
+    if gcf_dtype == "bf16":
+        return torch.from_numpy(st.view(np.int16)).to(device()).view(torch.bfloat16)
+    return torch.from_numpy(st).to(device())
+
+
+def stored_reference_inputs(p, grid_dtype, gcf_dtype):
+    """Subgrids and tables as the library receives them, widened to float64:
+    what the oracle must be given for a parity check of low-precision storage."""
+    sub = p.subgrids if grid_dtype == "c64" else \
+        wl.storage_to_complex128(wl.complex_to_storage(p.subgrids, grid_dtype), grid_dtype)
+    g_uv, g_w = wl.stored_tables(p, gcf_dtype)
+    return sub, g_uv, g_w
 
 
 def plan_for(p, **kw):

@@ -84,7 +84,7 @@ def _desc(dg, **kw):
 
 @pytest.mark.parametrize("kw,status", [
     (dict(os_uv=65), 1), (dict(os_w=0), 1), (dict(os_uv=128), 1), (dict(os_w=65), 1), (dict(flags=1), 1),
-    (dict(n_b=65), 1), (dict(n_b=-1), 1), (dict(grid_dtype=3), 1), (dict(gcf_dtype=2), 1),
+    (dict(n_b=65), 1), (dict(n_b=-1), 1), (dict(grid_dtype=3), 1), (dict(gcf_dtype=3), 1),
     (dict(n_v=7), 1), (dict(support_uv=6), 2), (dict(support_w=6), 2), (dict(n_w=3), 1),
     (dict(support_uv=0), 1), (dict(n_v=8192, n_u=8192), 2),
 ])

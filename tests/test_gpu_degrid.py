@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from paper_2102_12739_amd import workload as wl
-from tests.gpu_common import REL_L2_FP32, announce, device, plan_for, rel_l2, upload
+from tests.gpu_common import REL_L2_FP32, announce, device, plan_for, rel_l2, stored_reference_inputs, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -231,7 +231,8 @@ def test_sorted_work_order_with_out_of_range_and_empty_subgrids():
     assert got[3] == 0 and got[10] == 0 and got[905] == 0
 
 
-@pytest.mark.parametrize("grid_dtype,gcf_dtype", [("c64", "f32"), ("cbf16", "f16"), ("cf16", "f32")])
+@pytest.mark.parametrize("grid_dtype,gcf_dtype", [("c64", "f32"), ("cbf16", "f16"), ("cf16", "f32"), ("cf16", "f16"),
+                                                 ("cbf16", "bf16")])
 def test_every_kernel_variant_gives_the_same_outputs(grid_dtype, gcf_dtype):
     """The variants differ only in where a tile's cells are read from (LDS copy
     of the tile's bounding box, or the caches); each visibility's arithmetic is
@@ -255,10 +256,8 @@ def test_every_kernel_variant_gives_the_same_outputs(grid_dtype, gcf_dtype):
                 assert plan.oob_count() == 1
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
-    from paper_2102_12739_amd import workload as w2
-    deq = w2.storage_to_complex128(w2.complex_to_storage(p.subgrids, grid_dtype), grid_dtype)
-    tdt = np.float32 if gcf_dtype == "f32" else np.float16
-    ref, _ = oracle.degrid(deq, p.g_uv.astype(tdt), p.g_w.astype(tdt), p.uvw, p.offsets)
+    sub, g_uv, g_w = stored_reference_inputs(p, grid_dtype, gcf_dtype)
+    ref, _ = oracle.degrid(sub, g_uv, g_w, p.uvw, p.offsets)
     assert rel_l2(outs[0], ref) <= REL_L2_FP32
     assert outs[0][7] == 0
     with pytest.raises(Exception):

@@ -102,3 +102,21 @@ def test_count_profiles_of_the_two_scenarios():
     assert np.all(np.diff(ramp) > 0)
     with pytest.raises(ValueError):
         wl.count_profile("uniform", 4, 8)
+
+
+def test_table_storage_rounds_once_and_widens_exactly():
+    t = wl.gcf_uv(16)
+    for dt, rel in (("f32", 0.0), ("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)):
+        st = wl.table_to_storage(t, dt)
+        back = wl.storage_table_to_f64(st, dt)
+        assert back.dtype == np.float64 and back.shape == t.shape
+        # widening is exact: storing the widened values again changes nothing
+        assert np.array_equal(wl.table_to_storage(back, dt), st)
+        normal = np.abs(t) >= 2.0 ** -14        # fp16's smallest normal
+        assert np.all(np.abs(back - t)[normal] <= rel * np.abs(t)[normal] + 1e-30)
+    bits = wl.table_to_storage(np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8]), "bf16")
+    assert list(wl.storage_table_to_f64(bits, "bf16")) == [1.0, 1.0, 1.0 + 2.0 ** -6]   # ties to even
+    p = wl.plain_line(seed=0)
+    g_uv, g_w = wl.stored_tables(p, "bf16")
+    assert np.array_equal(g_w, wl.storage_table_to_f64(wl.to_bf16_bits(p.g_w), "bf16"))
+    assert g_uv.shape == p.g_uv.shape
