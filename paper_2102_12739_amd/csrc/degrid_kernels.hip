@@ -119,8 +119,14 @@ __device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, i
 // next tile's header and visibility indices are requested when the current
 // tile starts, its coordinates while the current tile is gathered, and the
 // tile after it is popped from the queue one tile ahead.
+// Workgroups per CU the register allocation must allow: three for 16-bit
+// storage gathered through the caches (no LDS box, and about 170 registers
+// before the bound: the third wavefront per SIMD hides more latency than the
+// few values moved to scratch cost), two otherwise.
+constexpr int degrid_min_blocks(int grid_kind, int box) { return (grid_kind != kGridC64 && box == 0) ? 3 : 2; }
+
 template <int G, int F, int BOX, int NB, bool DEEP>
-__global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P) {
+__global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degrid_kernel(LaunchParams P) {
     using GT = GridTraits<G>;
     static_assert(NB % 8 == 0 && NB <= kMaxNb, "tile size");
     constexpr int kBoxBytes = BOX > 0 ? BOX : 16;
@@ -214,10 +220,8 @@ __global__ __launch_bounds__(kBlockThreads, 2) void degrid_kernel(LaunchParams P
         if (BOX > 0 && pr.n_w == kSupportW) {
             // bounding box of the tile's neighbourhoods (the box holds w 0..3
             // of each cell, so only subgrids of 4 w planes are staged)
-            bx0 = uniform(wave_min(in_range ? x0 : 0x7FFFFFFF));
-            by0 = uniform(wave_min(in_range ? y0 : 0x7FFFFFFF));
-            const int bx1 = uniform(wave_max(in_range ? x0 : -1));
-            const int by1 = uniform(wave_max(in_range ? y0 : -1));
+            int bx1 = -1, by1 = -1;
+            wave_bbox(in_range, x0, y0, bx0, by0, bx1, by1);
             if (bx1 >= 0) {
                 bw = bx1 - bx0 + kSupportUV;
                 bh = by1 - by0 + kSupportUV;

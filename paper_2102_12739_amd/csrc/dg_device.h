@@ -330,15 +330,44 @@ __device__ __forceinline__ void reduce8(float (&p)[8]) {
 // Degrid kernel
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int wave_min(int x) {
+// Minimum over the 64 lanes of four values at once, on every lane: the lane
+// exchanges of reduce8 (permlane swaps 32 and 16 lanes apart, then four DPP
+// steps inside rows of 16) with min in place of the sum, the four chains in
+// lockstep so that each step's latency hides behind the other three. All
+// VALU, no LDS traffic. Call with every lane active.
+__device__ __forceinline__ void wave_min4(int (&v)[4]) {
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x = min(x, __shfl_xor(x, m));
-    return x;
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap((uint32_t)v[i], (uint32_t)v[i], false, false);
+        v[i] = min((int)r[0], (int)r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap((uint32_t)v[i], (uint32_t)v[i], false, false);
+        v[i] = min((int)r[0], (int)r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = min(v[i], __builtin_amdgcn_update_dpp(0, v[i], kDppRowRor8, 0xF, 0xF, false));
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        v[i] = min(v[i], __builtin_amdgcn_update_dpp(0, v[i], kDppRowHalfMirror, 0xF, 0xF, false));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = min(v[i], __builtin_amdgcn_update_dpp(0, v[i], kDppQuadXor2, 0xF, 0xF, false));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = min(v[i], __builtin_amdgcn_update_dpp(0, v[i], kDppQuadXor1, 0xF, 0xF, false));
 }
-__device__ __forceinline__ int wave_max(int x) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x = max(x, __shfl_xor(x, m));
-    return x;
+
+// Bounding box of the start cells (x, y) of the lanes with valid set, as
+// wavefront-uniform values; x1 = -1 when no lane is valid.
+__device__ __forceinline__ void wave_bbox(bool valid, int x, int y, int& x0, int& y0, int& x1, int& y1) {
+    constexpr int kNone = 0x7FFFFFFF;
+    // maxima as minima of the negated values (start cells are >= 0)
+    int v[4] = {valid ? x : kNone, valid ? y : kNone, valid ? -x : 1, valid ? -y : 1};
+    wave_min4(v);
+    x0 = uniform(v[0]);
+    y0 = uniform(v[1]);
+    x1 = uniform(-v[2]);
+    y1 = uniform(-v[3]);
 }
 
 // Scalar-cache view of read-only data: loads through it with a wave-uniform

@@ -80,10 +80,8 @@ __global__ __launch_bounds__(kBlockThreads) void grid_adjoint_kernel(LaunchParam
         bool staged = false;
         int bx0 = 0, by0 = 0, bw = 0, bh = 0, bp = 0;
         if (BOX > 0 && pr.n_w == kSupportW) {   // the box holds w 0..3 of each cell
-            bx0 = uniform(wave_min(in_range ? x0 : 0x7FFFFFFF));
-            by0 = uniform(wave_min(in_range ? y0 : 0x7FFFFFFF));
-            const int bx1 = uniform(wave_max(in_range ? x0 : -1));
-            const int by1 = uniform(wave_max(in_range ? y0 : -1));
+            int bx1 = -1, by1 = -1;
+            wave_bbox(in_range, x0, y0, bx0, by0, bx1, by1);
             if (bx1 >= 0) {
                 bw = bx1 - bx0 + kSupportUV;
                 bh = by1 - by0 + kSupportUV;
