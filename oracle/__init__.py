@@ -56,6 +56,8 @@ def _load():
     lib.oracle_degrid.restype = i64
     lib.oracle_grid.argtypes = args
     lib.oracle_grid.restype = i64
+    lib.oracle_table_grad.argtypes = [i64, i32, i32, i32, i32, i32, i32, i32, d, d, d, d, d, d, d, d]
+    lib.oracle_table_grad.restype = i64
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = i32
     lib.oracle_set_num_threads.argtypes = [i32]
@@ -133,3 +135,25 @@ def grid(vis, g_uv, g_w, uvw, offsets, shape):
                               v.ctypes.data, g_uv.ctypes.data, g_w.ctypes.data,
                               uvw.ctypes.data, offsets.ctypes.data, out.ctypes.data)
     return out[..., 0] + 1j * out[..., 1], int(oob)
+
+
+def table_grad(subgrids, g_uv, g_w, uvw, offsets, grad_vis):
+    """Gradients of a real loss with respect to ``G_uv`` and ``G_w`` in FP64,
+    given ``grad_vis`` = dL/dRe(V) + i dL/dIm(V) (complex ``[N]``).
+
+    Returns ``(grad_g_uv [os][os][W][W], grad_g_w [os_w][Ww], out_of_range_count)``.
+    """
+    g_uv, g_w, uvw, offsets, os_uv, su, os_w, sw = _check(g_uv, g_w, uvw, offsets)
+    a = _complex_as_pairs(subgrids)
+    s, n_v, n_u, n_w = a.shape[:4]
+    if s != len(offsets) - 1:
+        raise ValueError("offsets must have S+1 entries")
+    gv = _complex_as_pairs(grad_vis)
+    if gv.shape != (int(offsets[-1]), 2):
+        raise ValueError("grad_vis must have offsets[-1] entries")
+    out_uv = np.zeros(g_uv.shape, dtype=np.float64)
+    out_w = np.zeros(g_w.shape, dtype=np.float64)
+    oob = _load().oracle_table_grad(s, n_v, n_u, n_w, su, sw, os_uv, os_w,
+                                    a.ctypes.data, g_uv.ctypes.data, g_w.ctypes.data, uvw.ctypes.data,
+                                    offsets.ctypes.data, gv.ctypes.data, out_uv.ctypes.data, out_w.ctypes.data)
+    return out_uv, out_w, int(oob)

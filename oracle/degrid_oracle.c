@@ -165,6 +165,63 @@ int64_t oracle_grid(int64_t n_sub, int32_t n_v, int32_t n_u, int32_t n_w,
     return oob;
 }
 
+/*
+ * Gradients of a real loss L with respect to the two tables, given its
+ * gradient with respect to the visibilities, grad_vis[i] = dL/dRe(V_i) +
+ * i dL/dIm(V_i) (pairs re, im). Each visibility is linear in each table
+ * (real weights, complex values), so by the chain rule
+ *   dL/dG_uv[o_v][o_u][t_v][t_u] = sum over in-range i with offsets (o_v, o_u) of
+ *       Re(conj(grad_vis[i]) * sum_tw G_w[o_w][t_w] * A[y+t_v][x+t_u][z+t_w]),
+ *   dL/dG_w[o_w][t_w] = sum over in-range i with offset o_w of
+ *       Re(conj(grad_vis[i]) * sum_{t_v,t_u} G_uv[o_v][o_u][t_v][t_u] * A[y+t_v][x+t_u][z+t_w]),
+ * where Re(conj(g) * c) = g.re * c.re + g.im * c.im. Out-of-range
+ * visibilities add nothing. grad_g_uv ([os][os][W][W]) and grad_g_w
+ * ([os_w][Ww]) are overwritten; either may be NULL. One serial pass over
+ * the visibilities. Returns the out-of-range count.
+ */
+int64_t oracle_table_grad(int64_t n_sub, int32_t n_v, int32_t n_u, int32_t n_w,
+                          int32_t support_uv, int32_t support_w, int32_t os_uv, int32_t os_w,
+                          const double* subgrids, const double* g_uv, const double* g_w,
+                          const double* uvw, const int64_t* offsets, const double* grad_vis,
+                          double* grad_g_uv, double* grad_g_w)
+{
+    oracle_geom g = { n_sub, n_v, n_u, n_w, support_uv, support_w, os_uv, os_w };
+    if (grad_g_uv)
+        memset(grad_g_uv, 0, sizeof(double) * (size_t)os_uv * os_uv * support_uv * support_uv);
+    if (grad_g_w)
+        memset(grad_g_w, 0, sizeof(double) * (size_t)os_w * support_w);
+    int64_t oob = 0;
+    for (int64_t s = 0; s < n_sub; ++s) {
+        for (int64_t i = offsets[s]; i < offsets[s + 1]; ++i) {
+            int64_t x, y, z;
+            int32_t o_u, o_v, o_w;
+            if (!visibility_coordinates(&g, uvw + 3 * i, &x, &y, &z, &o_u, &o_v, &o_w)) {
+                oob += 1;
+                continue;
+            }
+            const double gre = grad_vis[2 * i], gim = grad_vis[2 * i + 1];
+            const int64_t uv_row = ((int64_t)o_v * os_uv + o_u) * support_uv * support_uv;
+            const double* gw = g_w + (int64_t)o_w * support_w;
+            for (int32_t tv = 0; tv < support_uv; ++tv)
+                for (int32_t tu = 0; tu < support_uv; ++tu) {
+                    const double guv = g_uv[uv_row + tv * support_uv + tu];
+                    double c_re = 0.0, c_im = 0.0;   /* sum over t_w of G_w * A */
+                    for (int32_t tw = 0; tw < support_w; ++tw) {
+                        int64_t cell = ((s * n_v + (y + tv)) * n_u + (x + tu)) * n_w + (z + tw);
+                        const double a_re = subgrids[2 * cell], a_im = subgrids[2 * cell + 1];
+                        c_re += gw[tw] * a_re;
+                        c_im += gw[tw] * a_im;
+                        if (grad_g_w)
+                            grad_g_w[(int64_t)o_w * support_w + tw] += guv * (gre * a_re + gim * a_im);
+                    }
+                    if (grad_g_uv)
+                        grad_g_uv[uv_row + tv * support_uv + tu] += gre * c_re + gim * c_im;
+                }
+        }
+    }
+    return oob;
+}
+
 /* Threads an OpenMP parallel region of the oracle uses. */
 int32_t oracle_num_threads(void)
 {

@@ -37,6 +37,14 @@ MUTANTS = {
                                     "double* out = subgrids_out + 2 * s * cells_per_sub;\n        if (s) out = subgrids_out;\n        memset"),
     "w_start_not_offset": ("double first = n - (double)(support / 2 - 1);",
                            "double first = (support == 4) ? n : n - (double)(support / 2 - 1);"),
+    "tgrad_conj_sign": ("grad_g_uv[uv_row + tv * support_uv + tu] += gre * c_re + gim * c_im;",
+                        "grad_g_uv[uv_row + tv * support_uv + tu] += gre * c_re - gim * c_im;"),
+    "tgrad_taps_transposed": ("grad_g_uv[uv_row + tv * support_uv + tu] += gre",
+                              "grad_g_uv[uv_row + tu * support_uv + tv] += gre"),
+    "tgrad_w_missing_uv_weight": ("+= guv * (gre * a_re + gim * a_im);", "+= (gre * a_re + gim * a_im);"),
+    "tgrad_w_taps_reversed": ("grad_g_w[(int64_t)o_w * support_w + tw] +=",
+                              "grad_g_w[(int64_t)o_w * support_w + (support_w - 1 - tw)] +="),
+    "tgrad_w_sum_skips_last_tap": ("c_re += gw[tw] * a_re;", "c_re += (tw < support_w - 1) ? gw[tw] * a_re : 0.0;"),
 }
 
 

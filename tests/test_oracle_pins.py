@@ -356,6 +356,77 @@ def test_p7_gradient_matches_exact_central_difference(oracle_mod):
 
 
 # ---------------------------------------------------------------------------
+# P12: gradients with respect to the tables
+# ---------------------------------------------------------------------------
+
+def _table_loss(oracle_mod, a, g_uv, g_w, uvw, offsets, g):
+    """L = sum_i Re(conj(g_i) V_i): its gradient with respect to V is g."""
+    v, _ = oracle_mod.degrid(a, g_uv, g_w, uvw, offsets)
+    return float(np.sum(g.real * v.real + g.imag * v.imag))
+
+
+@pytest.mark.parametrize("os_uv,os_w,n_w", [(8, 16, 4), (6, 5, 7)])
+def test_p12_table_gradient_equals_exact_central_difference(oracle_mod, os_uv, os_w, n_w):
+    """V is linear in each table, so a central difference with h = 1 is exact
+    (rounding only). Checked on every G_w entry and on G_uv entries drawn at
+    random plus whole blocks (o_v, o_u); an entry no visibility uses has a
+    difference of exactly zero, and so must its gradient."""
+    rng, uvw, offsets, g_uv, g_w, a, _ = _medium_case(130 + n_w, os_uv=os_uv, os_w=os_w, n_v=20, n_u=22,
+                                                      n_w=n_w, counts=(30, 0, 25))
+    uvw[3, 0] = 1.5            # out of range: adds nothing
+    g_uv, g_w = g_uv.astype(np.float64), g_w.astype(np.float64)   # so that G +- 1 is exact
+    g = rng.standard_normal(len(uvw)) + 1j * rng.standard_normal(len(uvw))
+    grad_uv, grad_w, oob = oracle_mod.table_grad(a, g_uv, g_w, uvw, offsets, g)
+    assert oob == 1
+    assert grad_uv.shape == g_uv.shape and grad_w.shape == g_w.shape
+    scale = float(np.sum(np.abs(g))) * float(np.max(np.abs(a))) * 64 * 4
+
+    def check(table_is_uv, idx):
+        base = g_uv if table_is_uv else g_w
+        plus, minus = base.copy(), base.copy()
+        plus[idx] += 1.0
+        minus[idx] -= 1.0
+        args = (lambda t: (t, g_w)) if table_is_uv else (lambda t: (g_uv, t))
+        lp = _table_loss(oracle_mod, a, *args(plus), uvw, offsets, g)
+        lm = _table_loss(oracle_mod, a, *args(minus), uvw, offsets, g)
+        dl = (lp - lm) / 2.0
+        got = (grad_uv if table_is_uv else grad_w)[idx]
+        if dl == 0.0:
+            assert got == 0.0, idx
+        assert abs(dl - got) <= 1e-12 * scale, (table_is_uv, idx, dl, got)
+        return dl != 0.0
+
+    for idx in np.ndindex(g_w.shape):
+        check(False, idx)
+    used = 0
+    for _ in range(40):
+        idx = tuple(int(rng.integers(n)) for n in g_uv.shape)
+        used += check(True, idx)
+    # whole blocks: every tap of a few (o_v, o_u) offsets, used or not
+    for ov, ou in ((0, 0), (os_uv - 1, os_uv - 1), (1, os_uv // 2)):
+        for tv in range(W):
+            for tu in range(W):
+                check(True, (ov, ou, tv, tu))
+    assert used > 0
+    assert np.count_nonzero(grad_uv) < grad_uv.size   # some offsets no visibility uses
+
+
+def test_p12_table_gradient_euler_identity(oracle_mod):
+    """V is homogeneous of degree one in each table, so for L = Re<g, V>:
+    sum(G_uv * dL/dG_uv) = L = sum(G_w * dL/dG_w)."""
+    rng, uvw, offsets, g_uv, g_w, a, _ = _medium_case(140, os_uv=16, os_w=16, counts=(300, 0, 220))
+    g = rng.standard_normal(len(uvw)) + 1j * rng.standard_normal(len(uvw))
+    grad_uv, grad_w, _ = oracle_mod.table_grad(a, g_uv, g_w, uvw, offsets, g)
+    loss = _table_loss(oracle_mod, a, g_uv, g_w, uvw, offsets, g)
+    scale = float(np.sum(np.abs(g))) * float(np.max(np.abs(a)))
+    assert abs(float(np.sum(g_uv * grad_uv)) - loss) <= 1e-12 * scale
+    assert abs(float(np.sum(g_w * grad_w)) - loss) <= 1e-12 * scale
+    # the two outputs are independent: asking for one leaves the other alone
+    uv_only, w_only, _ = oracle_mod.table_grad(a, g_uv, g_w, uvw, offsets, g)
+    assert np.array_equal(uv_only, grad_uv) and np.array_equal(w_only, grad_w)
+
+
+# ---------------------------------------------------------------------------
 # P10, P11: FP64 index exactness and out-of-range handling
 # ---------------------------------------------------------------------------
 
