@@ -519,7 +519,8 @@ def bench_differentiation(steps, warmup, check):
     gridding adjoint through torch.autograd). Also checks, on the GPU
     outputs with float64 sums on the host, the adjoint identity
     <degrid A, V> = <A, grid V> and the gradient against central
-    differences (exact for a quadratic loss) at 64 random points."""
+    differences (exact for a quadratic loss) at 64 random points, and times
+    the gradients with respect to both tables (checked against the oracle's)."""
     import numpy as np
     import torch
     from paper_2102_12739_amd import workload as wl
@@ -556,6 +557,8 @@ def bench_differentiation(steps, warmup, check):
     loss_buf = torch.empty((), dtype=torch.float64, device=dev)
     vin = torch.from_numpy(wl.complex_noise(5, p.n_vis, 1.0).astype(np.complex64)).to(dev)
     gout = torch.empty(plan.shape, dtype=torch.complex64, device=dev)
+    tg_uv = torch.empty(g_uv.shape, dtype=torch.float32, device=dev)
+    tg_w = torch.empty(g_w.shape, dtype=torch.float32, device=dev)
     res = {"workload": "differentiation-S16-65536-uniform", "visibilities": p.n_vis,
            "v_obs": "oracle degrid of the true subgrids + N(0, 0.01^2) per component" if check
            else "GPU degrid of the true subgrids + N(0, 0.01^2) per component"}
@@ -564,7 +567,9 @@ def bench_differentiation(steps, warmup, check):
                      ("residual_and_loss", lambda: plan.residual(a.detach(), g_uv, g_w, uvw, v_obs, out=res_buf,
                                                                  loss=loss_buf)),
                      ("degrid", lambda: plan.execute(sub, g_uv, g_w, uvw, out=out)),
-                     ("adjoint", lambda: plan.adjoint(vin, g_uv, g_w, uvw, out=gout))):
+                     ("adjoint", lambda: plan.adjoint(vin, g_uv, g_w, uvw, out=gout)),
+                     ("table_gradients", lambda: plan.table_grad(sub, g_uv, g_w, uvw, vin, out_uv=tg_uv,
+                                                                 out_w=tg_w))):
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -621,9 +626,15 @@ def bench_differentiation(steps, warmup, check):
         ref, _ = oracle.grid(2.0 * (r - vo), p.g_uv, p.g_w, p.uvw, p.offsets, plan.shape)
         got = a.grad.cpu().numpy()
         res["gradient_rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        # table gradients of L = Re<vin, degrid(A_true)> against the oracle's
+        gu, gw = plan.table_grad(sub, g_uv, g_w, uvw, vin)
+        ref_uv, ref_w, _ = oracle.table_grad(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets, vin.cpu().numpy())
+        res["table_gradients"]["rel_l2_g_uv"] = float(np.linalg.norm(gu.cpu().numpy() - ref_uv) / np.linalg.norm(ref_uv))
+        res["table_gradients"]["rel_l2_g_w"] = float(np.linalg.norm(gw.cpu().numpy() - ref_w) / np.linalg.norm(ref_w))
     log(f"differentiation: forward+backward {res['forward_backward']['ms_per_step']:.3f} ms "
         f"(fused {res['fused_forward_backward']['ms_per_step']:.3f} ms), "
-        f"adjoint {res['adjoint']['ms_per_step']:.3f} ms, identity {res['adjoint_identity_rel']:.2e}, "
+        f"adjoint {res['adjoint']['ms_per_step']:.3f} ms, table gradients {res['table_gradients']['ms_per_step']:.3f} ms, "
+        f"identity {res['adjoint_identity_rel']:.2e}, "
         f"fd {res['finite_difference']['max_abs_err_over_max_grad']:.2e}")
     return res
 

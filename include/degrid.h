@@ -151,6 +151,27 @@ dg_status degrid_execute(dg_plan p, const void* subgrids, const void* g_uv, cons
                          const double* uvw, void* vis_out, hipStream_t stream);
 
 /*
+ * Gradients with respect to the tables (the chain rule through the weighted
+ * sum of Section 2; each visibility is linear in each table). Given the
+ * gradient of a real loss L with respect to the visibilities,
+ * grad_vis[i] = dL/dRe(V_i) + i dL/dIm(V_i) (device complex float32 [N]):
+ *   grad_g_uv[o_v][o_u][t_v][t_u] = sum over in-range i with offsets (o_v, o_u) of
+ *       Re(conj(grad_vis[i]) * sum_tw G_w[o_w][t_w] * A[y+t_v][x+t_u][z+t_w]);
+ *   grad_g_w[o_w][t_w] = sum over in-range i with offset o_w of
+ *       Re(conj(grad_vis[i]) * sum_{t_v,t_u} G_uv[o_v][o_u][t_v][t_u] * A[...]).
+ *   grad_g_uv  device float32 [os_uv][os_uv][8][8], or NULL (not computed).
+ *   grad_g_w   device float32 [os_w][4], or NULL (not computed).
+ *   accumulate 0: the outputs are overwritten; 1: added to.
+ * Other arguments as for degrid_execute, in the plan's dtypes. Out-of-range
+ * visibilities add nothing. The sums meet in float32 atomics, so the last
+ * bits depend on timing. Both outputs 4-byte aligned. Asynchronous on
+ * 'stream'; allocates nothing.
+ */
+dg_status degrid_table_grad(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w, const double* uvw,
+                            const void* grad_vis, float* grad_g_uv, float* grad_g_w, int32_t accumulate,
+                            hipStream_t stream);
+
+/*
  * Residual and loss in the same pass as the degrid (the imaging major cycle
  * of Section 1 subtracts the model visibilities from the observed ones):
  *   res_out[i] = v_obs[i] - degrid(subgrids)_i   (complex float32 [N]);

@@ -578,6 +578,51 @@ dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void*
     return DG_OK;
 }
 
+dg_status degrid_table_grad(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w, const double* uvw,
+                            const void* grad_vis, float* grad_g_uv, float* grad_g_w, int32_t accumulate,
+                            hipStream_t stream) {
+    if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");
+    if (accumulate != 0 && accumulate != 1) return fail(DG_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+    if (!grad_g_uv && !grad_g_w) return DG_OK;   // nothing asked for
+    for (const void* q : {static_cast<const void*>(grad_g_uv), static_cast<const void*>(grad_g_w)})
+        if (q && reinterpret_cast<uintptr_t>(q) % 4 != 0)
+            return fail(DG_ERR_INVALID_ARG, "table gradient outputs must be 4-byte aligned");
+    const dg_desc& d = p->desc;
+    const int64_t n_uv = (int64_t)d.os_uv * d.os_uv * kSupportUV * kSupportUV;
+    const int64_t n_w = (int64_t)d.os_w * kSupportW;
+    if (p->ds.n_tiles > 0) {
+        if (!subgrids || !g_uv || !g_w || !uvw || !grad_vis)
+            return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+        if (dg_status s = check_alignment(d, subgrids, g_uv, g_w, uvw, nullptr, grad_vis, nullptr); s != DG_OK)
+            return s;
+    }
+    hipError_t e = hipSuccess;
+    if (!accumulate) {
+        if (grad_g_uv) e = launch_zero_f32(grad_g_uv, n_uv, stream);
+        if (e == hipSuccess && grad_g_w) e = launch_zero_f32(grad_g_w, n_w, stream);
+        if (e != hipSuccess) return hip_fail(e, "zero-fill kernel launch");
+    }
+    if (p->ds.n_tiles == 0) return DG_OK;
+    TableGradParams tp{};
+    tp.prob = problem_of(p, subgrids, g_uv, g_w, uvw, const_cast<void*>(grad_vis), nullptr);
+    tp.tiles = p->ds.tiles;
+    tp.tile_vis = p->ds.tile_vis;
+    tp.n_tiles = p->ds.n_tiles;
+    tp.grad_uv = grad_g_uv;
+    tp.grad_w = grad_g_w;
+    int waves = 0;
+    size_t lds = 0;
+    table_grad_shape(d.os_w, grad_g_w != nullptr, &waves, &lds);
+    // grid-stride over the tiles; a few workgroups per CU keep every SIMD busy
+    const int64_t blocks = std::max<int64_t>(
+        1, std::min<int64_t>((p->ds.n_tiles + waves - 1) / waves, (int64_t)std::max(1, p->n_cu) * 2 * (kWavesPerBlock / waves)));
+    e = launch_table_grad(tp, d.grid_dtype, d.gcf_dtype, deep_only(d), (int)blocks, stream);
+    if (e != hipSuccess) return hip_fail(e, "table gradient kernel launch");
+    p->last_stream = stream;
+    p->launched = true;
+    return DG_OK;
+}
+
 dg_status degrid_oob_count(dg_plan p, int64_t* count) {
     if (!p || !count) return fail(DG_ERR_INVALID_ARG, "plan or count is NULL");
     *count = 0;

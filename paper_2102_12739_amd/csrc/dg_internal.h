@@ -89,10 +89,22 @@ struct OwnerParams {
     int32_t nby, nbx;              // blocks per subgrid along v and u
 };
 
+// Table-gradient pass: dL/dG_uv and dL/dG_w from dL/dV over the tiles of a
+// plan (prob.vis holds dL/dV, complex float32 [N]).
+struct TableGradParams {
+    Problem prob;
+    const Tile* tiles;
+    const uint32_t* tile_vis;
+    int64_t n_tiles;
+    float* grad_uv;   // [os_uv][os_uv][8][8], or nullptr
+    float* grad_w;    // [os_w][4], or nullptr
+};
+
 enum GridKind : int32_t { kGridC64 = 0, kGridCBF16 = 1, kGridCF16 = 2 };
 enum GcfKind : int32_t { kGcfF32 = 0, kGcfF16 = 1, kGcfBF16 = 2 };
 
-// Kernel launchers (defined in degrid_kernels.hip and grid_kernels.hip).
+// Kernel launchers (defined in degrid_kernels.hip, grid_kernels.hip and
+// table_grad_kernels.hip).
 hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int variant,
                          int blocks, hipStream_t stream);
 hipError_t launch_grid_adjoint(const LaunchParams& p, int gcf_kind, int variant, int blocks,
@@ -138,5 +150,13 @@ int adjoint_variant_count();
 int degrid_variant_box_bytes(int variant);   // LDS staging bytes per wavefront (0: none)
 int degrid_variant_max_nb(int variant);      // largest tile the variant accepts
 constexpr int kMaxVariants = 8;
+// Adds dL/dG_uv and dL/dG_w of every in-range visibility to p.grad_uv and
+// p.grad_w (float atomics). deep: subgrids with more w planes than the support.
+hipError_t launch_table_grad(const TableGradParams& p, int grid_kind, int gcf_kind, bool deep, int blocks,
+                             hipStream_t stream);
+// Wavefronts per workgroup and dynamic LDS bytes of that kernel.
+void table_grad_shape(int os_w, bool want_w, int* waves, size_t* lds_bytes);
+// p[0 .. n) = 0.0f (a kernel, so that graphs may capture it).
+hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t stream);
 
 }  // namespace dg

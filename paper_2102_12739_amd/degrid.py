@@ -76,6 +76,7 @@ def lib():
         "degrid_execute": ([vp, vp, vp, vp, vp, vp, vp], i32),
         "degrid_residual": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "grid_adjoint": ([vp, vp, vp, vp, vp, vp, i32, vp], i32),
+        "degrid_table_grad": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
         "degrid_oob_count": ([vp, ctypes.POINTER(ctypes.c_int64)], i32),
         "degrid_plan_get_info": ([vp, ctypes.POINTER(DgPlanInfo)], i32),
         "degrid_plan_sort": ([vp, vp, vp], i32),
@@ -225,6 +226,31 @@ class Plan:
                                   _stream_handle(stream)), "grid_adjoint")
         return out
 
+    def table_grad(self, subgrids, g_uv, g_w, uvw, grad_vis, want_uv: bool = True, want_w: bool = True,
+                   out_uv=None, out_w=None, accumulate: bool = False, stream=None):
+        """Gradients of a real loss with respect to the tables from ``grad_vis``
+        = dL/dRe(V) + i dL/dIm(V) (complex64 ``[N]``).
+
+        Returns ``(grad_g_uv float32 [os_uv, os_uv, 8, 8], grad_g_w float32
+        [os_w, 4])``, with ``None`` for a table not asked for.
+        """
+        ps = _ptr(subgrids, "subgrids", _grid_tensor_dtype(self.grid_dtype), self._grid_shape())
+        pg, pw = self._check_tables(g_uv, g_w)
+        pu = self._check_uvw(uvw)
+        pv = _ptr(grad_vis, "grad_vis", torch.complex64, (self.n_vis,))
+        dev = uvw.device
+        if want_uv and out_uv is None:
+            out_uv = torch.empty((self.os_uv, self.os_uv, 8, 8), dtype=torch.float32, device=dev)
+            accumulate = False
+        if want_w and out_w is None:
+            out_w = torch.empty((self.os_w, 4), dtype=torch.float32, device=dev)
+            accumulate = False
+        po_uv = _ptr(out_uv, "out_uv", torch.float32, (self.os_uv, self.os_uv, 8, 8)) if want_uv else None
+        po_w = _ptr(out_w, "out_w", torch.float32, (self.os_w, 4)) if want_w else None
+        _check(lib().degrid_table_grad(self._handle, ps, pg, pw, pu, pv, po_uv, po_w, int(bool(accumulate)),
+                                       _stream_handle(stream)), "degrid_table_grad")
+        return (out_uv if want_uv else None), (out_w if want_w else None)
+
     def tune(self, subgrids, g_uv, g_w, uvw, out=None, stream=None):
         """Time tile sizes and kernel variants on these inputs; keep the fastest."""
         ps = _ptr(subgrids, "subgrids", _grid_tensor_dtype(self.grid_dtype), self._grid_shape())
@@ -342,23 +368,32 @@ class DegridFn(torch.autograd.Function):
 
     The map is real-linear with real weights W, so for PyTorch's complex
     gradient convention the vector-Jacobian product is ``W^T grad_vis``, i.e.
-    ``grid_adjoint(grad_vis)``. Gradients flow to ``subgrids`` only (the table
-    lookup is piecewise constant in ``uvw``; the tables are inputs).
+    ``grid_adjoint(grad_vis)``. The tables get their gradients from
+    ``degrid_table_grad`` (each visibility is linear in each table), returned
+    in the tables' dtype. ``uvw`` gets none: the table lookup is piecewise
+    constant in it.
     """
 
     @staticmethod
     def forward(ctx, subgrids, plan: Plan, g_uv, g_w, uvw):
         ctx.plan = plan
-        ctx.save_for_backward(g_uv, g_w, uvw)
+        ctx.save_for_backward(subgrids, g_uv, g_w, uvw)
         return plan.execute(subgrids, g_uv, g_w, uvw)
 
     @staticmethod
     def backward(ctx, grad_vis):
-        g_uv, g_w, uvw = ctx.saved_tensors
-        grad = None
+        subgrids, g_uv, g_w, uvw = ctx.saved_tensors
+        gv = grad_vis.contiguous().to(torch.complex64)
+        grad = grad_uv = grad_w = None
         if ctx.needs_input_grad[0]:
-            grad = ctx.plan.adjoint(grad_vis.contiguous().to(torch.complex64), g_uv, g_w, uvw)
-        return grad, None, None, None, None
+            grad = ctx.plan.adjoint(gv, g_uv, g_w, uvw)
+        want_uv, want_w = ctx.needs_input_grad[2], ctx.needs_input_grad[3]
+        if want_uv or want_w:
+            grad_uv, grad_w = ctx.plan.table_grad(subgrids.detach(), g_uv.detach(), g_w.detach(), uvw, gv,
+                                                  want_uv=want_uv, want_w=want_w)
+            grad_uv = grad_uv.to(g_uv.dtype) if grad_uv is not None else None
+            grad_w = grad_w.to(g_w.dtype) if grad_w is not None else None
+        return grad, None, grad_uv, grad_w, None
 
 
 class ResidualLossFn(torch.autograd.Function):
