@@ -203,15 +203,18 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
         const uint64_t g_w = uniform_u64((uint64_t)pr.g_w);
         const uint32_t lane_g = (uint32_t)lane * GcfTraits<F>::kBytes;
 
-        // G_uv weights of the whole tile (zero for out-of-range visibilities).
-        const int g_off = in_range ? tab * (int)GcfTraits<F>::kBytes : (int)kOutOfRange;
+        // G_uv weights of the whole tile. Visibility k's block offset goes in
+        // the load's scalar offset, so no per-visibility address add. An
+        // out-of-range visibility reads block 0: its sum is discarded, because
+        // the output stage writes 0 for it.
+        const int g_off = in_range ? tab * (int)GcfTraits<F>::kBytes : 0;
         float gv[NB];
 #pragma unroll
         for (int g0 = 0; g0 < NB; g0 += 8) {
             if (g0 < count) {
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
-                    gv[g0 + k] = load_gcf_rsrc<F>(rg, (uint32_t)__builtin_amdgcn_readlane(g_off, g0 + k) + lane_g);
+                    gv[g0 + k] = load_gcf_rsrc<F>(rg, lane_g, (uint32_t)__builtin_amdgcn_readlane(g_off, g0 + k));
             }
         }
 

@@ -210,12 +210,14 @@ __device__ __forceinline__ float widen_gcf16(uint32_t h) {
     else return __half2float(__builtin_bit_cast(__half, (unsigned short)h));
 }
 
+// One table value at byte offset off + soff (soff wave-uniform: it travels
+// in the load's scalar offset).
 template <int F>
-__device__ __forceinline__ float load_gcf_rsrc(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+__device__ __forceinline__ float load_gcf_rsrc(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0) {
     if constexpr (F == kGcfF32) {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
     } else {
-        return widen_gcf16<F>(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+        return widen_gcf16<F>(__builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0));
     }
 }
 
@@ -288,7 +290,9 @@ __device__ __forceinline__ bool vis_coords(const Problem& pr, int64_t i, int32_t
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+    // bound_ctrl: the patterns used never read outside a row, so lanes never
+    // take the old value, and none has to be set up
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 constexpr int kDppQuadXor1 = 0xB1;       // quad_perm [1,0,3,2]
 constexpr int kDppQuadXor2 = 0x4E;       // quad_perm [2,3,0,1]
