@@ -610,13 +610,18 @@ dg_status degrid_table_grad(dg_plan p, const void* subgrids, const void* g_uv, c
     tp.n_tiles = p->ds.n_tiles;
     tp.grad_uv = grad_g_uv;
     tp.grad_w = grad_g_w;
-    int waves = 0;
+    // grid-stride over the tiles with at most as many workgroups as fit at
+    // once (each one ends by adding its LDS sums to the outputs)
+    int max_lds = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(LDS per workgroup)");
+    bool lds_uv = false;
     size_t lds = 0;
-    table_grad_shape(d.os_w, grad_g_w != nullptr, &waves, &lds);
-    // grid-stride over the tiles; a few workgroups per CU keep every SIMD busy
+    table_grad_shape(d.os_uv, d.os_w, grad_g_uv != nullptr, grad_g_w != nullptr, (size_t)max_lds, &lds_uv, &lds);
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(2, (int64_t)(160 * 1024) / (int64_t)std::max<size_t>(lds, 1)));
     const int64_t blocks = std::max<int64_t>(
-        1, std::min<int64_t>((p->ds.n_tiles + waves - 1) / waves, (int64_t)std::max(1, p->n_cu) * 2 * (kWavesPerBlock / waves)));
-    e = launch_table_grad(tp, d.grid_dtype, d.gcf_dtype, deep_only(d), (int)blocks, stream);
+        1, std::min<int64_t>((p->ds.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)std::max(1, p->n_cu) * per_cu));
+    e = launch_table_grad(tp, d.grid_dtype, d.gcf_dtype, deep_only(d), (int)blocks, (size_t)max_lds, stream);
     if (e != hipSuccess) return hip_fail(e, "table gradient kernel launch");
     p->last_stream = stream;
     p->launched = true;

@@ -152,10 +152,12 @@ int degrid_variant_max_nb(int variant);      // largest tile the variant accepts
 constexpr int kMaxVariants = 8;
 // Adds dL/dG_uv and dL/dG_w of every in-range visibility to p.grad_uv and
 // p.grad_w (float atomics). deep: subgrids with more w planes than the support.
+// max_lds: the device's LDS bytes per workgroup.
 hipError_t launch_table_grad(const TableGradParams& p, int grid_kind, int gcf_kind, bool deep, int blocks,
-                             hipStream_t stream);
-// Wavefronts per workgroup and dynamic LDS bytes of that kernel.
-void table_grad_shape(int os_w, bool want_w, int* waves, size_t* lds_bytes);
+                             size_t max_lds, hipStream_t stream);
+// Dynamic LDS bytes of that kernel, and whether it accumulates dL/dG_uv in LDS.
+void table_grad_shape(int os_uv, int os_w, bool want_uv, bool want_w, size_t max_lds, bool* lds_uv,
+                      size_t* lds_bytes);
 // p[0 .. n) = 0.0f (a kernel, so that graphs may capture it).
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t stream);
 

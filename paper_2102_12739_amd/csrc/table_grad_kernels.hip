@@ -11,15 +11,17 @@
 // reads the 4 w values of its tap through bounds-checked buffer loads.
 //
 //  * dL/dG_uv: every visibility adds one value per lane to the 64 contiguous
-//    entries of its (o_v, o_u) block: one coalesced float atomic per
-//    visibility (the table is small and shared by all visibilities, so the
-//    adds have to meet in memory; float atomics make the order, and so the
-//    last bits, depend on timing);
-//  * dL/dG_w: each wavefront keeps a private LDS array [o_w][t_w][lane] and
-//    adds its lane's share of every visibility there (no two lanes share a
-//    slot, so there are no bank conflicts and no atomics); at the end it sums
-//    each row over the lanes and adds it to the output with one float atomic
-//    per row.
+//    entries of its (o_v, o_u) block. When the table fits (os_uv <= 16,
+//    64 KiB) the workgroup keeps its own copy in LDS and every other
+//    visibility adds there (one LDS float add, no two lanes on one entry;
+//    the copy is added to the output once at the end), the others straight
+//    to the output with one coalesced float atomic, so that the two atomic
+//    units work side by side. Float atomics make the order, and so the last
+//    bits, depend on timing;
+//  * dL/dG_w: each lane's four shares are summed over groups of eight lanes
+//    with three DPP steps, and the eight group sums are added to a private
+//    per-wavefront LDS array [o_w][t_w][8] (eight distinct slots per add);
+//    at the end each row is summed and added to the output.
 #include "dg_device.h"
 
 namespace dg {
@@ -53,19 +55,41 @@ __device__ __forceinline__ void grad_fetch(GradFetch<G>& f, int g0, int count, i
     }
 }
 
-template <int G, int F, bool DEEP>
+constexpr int kWGroups = 8;   // lane groups whose dL/dG_w sums reach LDS
+
+// Sum of x over the aligned group of eight lanes holding this lane (every
+// lane of the group gets it): quad exchanges, then the mirror inside each
+// half row pairs quad 0 with quad 1.
+__device__ __forceinline__ float sum8_lanes(float x) {
+    x += dpp<kDppQuadXor1>(x);
+    x += dpp<kDppQuadXor2>(x);
+    x += dpp<kDppRowHalfMirror>(x);
+    return x;
+}
+
+// LDS_UV: the workgroup accumulates dL/dG_uv in LDS (the table fits).
+template <int G, int F, bool DEEP, bool LDS_UV>
 __global__ __launch_bounds__(kBlockThreads) void table_grad_kernel(TableGradParams P) {
-    extern __shared__ float s_acc[];   // [waves][os_w * 4][64] when grad_w is wanted
+    // [n_uv] shared by the workgroup (LDS_UV), then [waves][os_w * 4][8]
+    extern __shared__ float s_acc[];
     const int lane = lane_id();
     const int waves = (int)(blockDim.x / kWave);
-    const int wv = (int)(threadIdx.x / kWave);
+    // wave-uniform as far as the compiler knows, so that the tile index and
+    // the buffer resources built from it stay in scalar registers (a
+    // divergent resource would wrap every buffer load in a loop)
+    const int wv = uniform((int)(threadIdx.x / kWave));
     const Problem& pr = P.prob;
     const bool want_uv = P.grad_uv != nullptr;
     const bool want_w = P.grad_w != nullptr;
     const int rows_w = pr.os_w * kSupportW;
-    float* acc = s_acc + (size_t)wv * rows_w * kWave;
+    const int n_uv = LDS_UV ? pr.os_uv * pr.os_uv * kSupportUV * kSupportUV : 0;
+    float* s_uv = s_acc;
+    float* acc = s_acc + n_uv + (size_t)wv * rows_w * kWGroups;
+    if (LDS_UV)
+        for (int i = (int)threadIdx.x; i < n_uv; i += (int)blockDim.x) s_uv[i] = 0.0f;
     if (want_w)
-        for (int r = 0; r < rows_w; ++r) acc[r * kWave + lane] = 0.0f;
+        for (int i = lane; i < rows_w * kWGroups; i += kWave) acc[i] = 0.0f;
+    __syncthreads();
 
     const uint64_t g_w = uniform_u64((uint64_t)pr.g_w);
     const __amdgpu_buffer_rsrc_t rg = make_rsrc(pr.g_uv, pr.guv_bytes);
@@ -115,29 +139,56 @@ __global__ __launch_bounds__(kBlockThreads) void table_grad_kernel(TableGradPara
                         const float4 gw = load_gw_row<F>(g_w, (uint32_t)__builtin_amdgcn_readlane((int)gw_off, j));
                         const float sr = gw.x * re[0] + gw.y * re[1] + gw.z * re[2] + gw.w * re[3];
                         const float si = gw.x * im[0] + gw.y * im[1] + gw.z * im[2] + gw.w * im[3];
-                        atomicAdd(P.grad_uv + __builtin_amdgcn_readlane(tab, j) + lane, gre * sr + gim * si);
+                        const int e = __builtin_amdgcn_readlane(tab, j) + lane;
+                        // LDS float atomics and global float atomics run in
+                        // different units at similar rates (about 120 cycles
+                        // per 64-lane add to LDS per CU): alternate visibilities
+                        // go to each, so that the two overlap
+                        if (LDS_UV && (k & 1) == 0)
+                            atomicAdd(s_uv + e, gre * sr + gim * si);
+                        else
+                            atomicAdd(P.grad_uv + e, gre * sr + gim * si);
                     }
                     if (want_w) {
                         const int row = __builtin_amdgcn_readlane(ow, j) * kSupportW;
                         const float gv = buf[cur].gv[k];
+                        float r[kSupportW];
 #pragma unroll
-                        for (int tw = 0; tw < kSupportW; ++tw) {
-                            float* slot = acc + (row + tw) * kWave + lane;
-                            *slot += gv * (gre * re[tw] + gim * im[tw]);
+                        for (int tw = 0; tw < kSupportW; ++tw) r[tw] = sum8_lanes(gv * (gre * re[tw] + gim * im[tw]));
+                        // lane 8m holds group m's sums; the slots are this
+                        // wavefront's own, and LDS operations of a wavefront
+                        // run in order
+                        if ((lane & (kWGroups - 1)) == 0) {
+#pragma unroll
+                            for (int tw = 0; tw < kSupportW; ++tw) acc[(row + tw) * kWGroups + (lane >> 3)] += r[tw];
                         }
                     }
                 }
             }
         }
     }
+    __syncthreads();
+    // Every workgroup ends at about the same time; each starts its flush at
+    // its own place in the table, so that the adds to one entry spread out
+    // instead of queueing behind each other.
+    if (LDS_UV) {
+        const int rot = (int)(((int64_t)blockIdx.x * n_uv) / (int64_t)gridDim.x);
+        for (int k = (int)threadIdx.x; k < n_uv; k += (int)blockDim.x) {
+            const int i = k + rot < n_uv ? k + rot : k + rot - n_uv;
+            const float v = s_uv[i];
+            if (v != 0.0f) atomicAdd(P.grad_uv + i, v);   // entries no visibility reached stay as they are
+        }
+    }
     if (want_w) {
-        wave_lds_sync();
-        // lane r sums row r over the 64 lanes' slots, starting at a different
-        // slot per row so that the 64 reads of one step fall on distinct banks
-        for (int r = lane; r < rows_w; r += kWave) {
+        // the workgroup's rows summed over its wavefronts and lane groups,
+        // then one add per row
+        const float* acc0 = s_acc + n_uv;
+        for (int r = (int)threadIdx.x; r < rows_w; r += (int)blockDim.x) {
             float s = 0.0f;
-            for (int j = 0; j < kWave; ++j) s += acc[r * kWave + ((j + r) & (kWave - 1))];
-            atomicAdd(P.grad_w + r, s);
+            for (int w = 0; w < waves; ++w)
+#pragma unroll
+                for (int m = 0; m < kWGroups; ++m) s += acc0[((size_t)w * rows_w + r) * kWGroups + m];
+            if (s != 0.0f) atomicAdd(P.grad_w + r, s);
         }
     }
 }
@@ -147,45 +198,48 @@ __global__ void zero_f32_kernel(float* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0f;
 }
 
-template <int G, int F, bool DEEP>
-hipError_t launch_tg(const TableGradParams& p, int blocks, int waves, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((table_grad_kernel<G, F, DEEP>), dim3(blocks), dim3(waves * kWave), lds, s, p);
+template <int G, int F, bool DEEP, bool LDS_UV>
+hipError_t launch_tg(const TableGradParams& p, int blocks, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((table_grad_kernel<G, F, DEEP, LDS_UV>), dim3(blocks), dim3(kBlockThreads), lds, s, p);
     return hipGetLastError();
 }
 
 template <int G, int F>
-hipError_t launch_tg_d(const TableGradParams& p, bool deep, int blocks, int waves, size_t lds, hipStream_t s) {
-    return deep ? launch_tg<G, F, true>(p, blocks, waves, lds, s) : launch_tg<G, F, false>(p, blocks, waves, lds, s);
+hipError_t launch_tg_d(const TableGradParams& p, bool deep, bool lds_uv, int blocks, size_t lds, hipStream_t s) {
+    if (deep)
+        return lds_uv ? launch_tg<G, F, true, true>(p, blocks, lds, s) : launch_tg<G, F, true, false>(p, blocks, lds, s);
+    return lds_uv ? launch_tg<G, F, false, true>(p, blocks, lds, s) : launch_tg<G, F, false, false>(p, blocks, lds, s);
 }
 
 }  // namespace
 
-// Wavefronts per workgroup and LDS bytes of the table-gradient kernel: each
-// wavefront's G_w accumulator takes os_w * 4 * 64 floats (16 KiB at os_w 16),
-// and a workgroup keeps within 64 KiB.
-void table_grad_shape(int os_w, bool want_w, int* waves, size_t* lds_bytes) {
-    const size_t per_wave = want_w ? (size_t)os_w * kSupportW * kWave * sizeof(float) : 0;
-    int w = kWavesPerBlock;
-    while (w > 1 && per_wave * (size_t)w > 65536) w /= 2;
-    *waves = w;
-    *lds_bytes = per_wave * (size_t)w;
+// LDS of the table-gradient kernel: the workgroup's copy of dL/dG_uv when it
+// is wanted, takes at most 64 KiB (os_uv <= 16) and the total fits max_lds
+// (the device's LDS per workgroup), and os_w * 4 * 8 floats per wavefront
+// for dL/dG_w.
+void table_grad_shape(int os_uv, int os_w, bool want_uv, bool want_w, size_t max_lds, bool* lds_uv,
+                      size_t* lds_bytes) {
+    const size_t uv = (size_t)os_uv * os_uv * kSupportUV * kSupportUV * sizeof(float);
+    const size_t w = want_w ? (size_t)kWavesPerBlock * os_w * kSupportW * kWGroups * sizeof(float) : 0;
+    *lds_uv = want_uv && uv <= 65536 && uv + w <= max_lds;
+    *lds_bytes = (*lds_uv ? uv : 0) + w;
 }
 
 hipError_t launch_table_grad(const TableGradParams& p, int grid_kind, int gcf_kind, bool deep, int blocks,
-                             hipStream_t stream) {
-    int waves = 0;
+                             size_t max_lds, hipStream_t stream) {
+    bool lds_uv = false;
     size_t lds = 0;
-    table_grad_shape(p.prob.os_w, p.grad_w != nullptr, &waves, &lds);
+    table_grad_shape(p.prob.os_uv, p.prob.os_w, p.grad_uv != nullptr, p.grad_w != nullptr, max_lds, &lds_uv, &lds);
     switch (grid_kind * 3 + gcf_kind) {
-        case kGridC64 * 3 + kGcfF32: return launch_tg_d<kGridC64, kGcfF32>(p, deep, blocks, waves, lds, stream);
-        case kGridC64 * 3 + kGcfF16: return launch_tg_d<kGridC64, kGcfF16>(p, deep, blocks, waves, lds, stream);
-        case kGridC64 * 3 + kGcfBF16: return launch_tg_d<kGridC64, kGcfBF16>(p, deep, blocks, waves, lds, stream);
-        case kGridCBF16 * 3 + kGcfF32: return launch_tg_d<kGridCBF16, kGcfF32>(p, deep, blocks, waves, lds, stream);
-        case kGridCBF16 * 3 + kGcfF16: return launch_tg_d<kGridCBF16, kGcfF16>(p, deep, blocks, waves, lds, stream);
-        case kGridCBF16 * 3 + kGcfBF16: return launch_tg_d<kGridCBF16, kGcfBF16>(p, deep, blocks, waves, lds, stream);
-        case kGridCF16 * 3 + kGcfF32: return launch_tg_d<kGridCF16, kGcfF32>(p, deep, blocks, waves, lds, stream);
-        case kGridCF16 * 3 + kGcfF16: return launch_tg_d<kGridCF16, kGcfF16>(p, deep, blocks, waves, lds, stream);
-        case kGridCF16 * 3 + kGcfBF16: return launch_tg_d<kGridCF16, kGcfBF16>(p, deep, blocks, waves, lds, stream);
+        case kGridC64 * 3 + kGcfF32: return launch_tg_d<kGridC64, kGcfF32>(p, deep, lds_uv, blocks, lds, stream);
+        case kGridC64 * 3 + kGcfF16: return launch_tg_d<kGridC64, kGcfF16>(p, deep, lds_uv, blocks, lds, stream);
+        case kGridC64 * 3 + kGcfBF16: return launch_tg_d<kGridC64, kGcfBF16>(p, deep, lds_uv, blocks, lds, stream);
+        case kGridCBF16 * 3 + kGcfF32: return launch_tg_d<kGridCBF16, kGcfF32>(p, deep, lds_uv, blocks, lds, stream);
+        case kGridCBF16 * 3 + kGcfF16: return launch_tg_d<kGridCBF16, kGcfF16>(p, deep, lds_uv, blocks, lds, stream);
+        case kGridCBF16 * 3 + kGcfBF16: return launch_tg_d<kGridCBF16, kGcfBF16>(p, deep, lds_uv, blocks, lds, stream);
+        case kGridCF16 * 3 + kGcfF32: return launch_tg_d<kGridCF16, kGcfF32>(p, deep, lds_uv, blocks, lds, stream);
+        case kGridCF16 * 3 + kGcfF16: return launch_tg_d<kGridCF16, kGcfF16>(p, deep, lds_uv, blocks, lds, stream);
+        case kGridCF16 * 3 + kGcfBF16: return launch_tg_d<kGridCF16, kGcfBF16>(p, deep, lds_uv, blocks, lds, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -52,11 +52,12 @@ def test_table_grad_matches_oracle(grid_dtype, gcf_dtype, sort):
     assert rel_l2(gw.cpu().numpy(), ref_w) <= REL_L2_GRAD
 
 
-@pytest.mark.parametrize("os_uv,os_w,n_w", [(6, 5, 4), (12, 40, 4), (16, 16, 7), (5, 64, 9)])
+@pytest.mark.parametrize("os_uv,os_w,n_w", [(6, 5, 4), (12, 40, 4), (16, 16, 7), (5, 64, 9), (24, 8, 4)])
 def test_table_grad_general_oversampling_and_deep_stacks(os_uv, os_w, n_w):
-    """Non-power-of-two oversampling, a G_w accumulator larger than one
-    workgroup's share of LDS (os_w 40 and 64: fewer wavefronts per
-    workgroup) and subgrids deeper than the w support."""
+    """Non-power-of-two oversampling, large G_w tables (os_w 40 and 64), a
+    G_uv table too large for a workgroup's LDS copy (os_uv 24: every
+    visibility adds straight to the output) and subgrids deeper than the w
+    support."""
     p = _problem(151 + os_w, os_uv=os_uv, os_w=os_w, n_w=n_w, counts=(1500, 700, 0, 900), n_v=40, n_u=48)
     announce(f"table grad os {os_uv}/{os_w} n_w {n_w}")
     t = upload(p)
