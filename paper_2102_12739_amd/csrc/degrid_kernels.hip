@@ -12,20 +12,29 @@
 //    Eq. (1));
 //  * each wavefront takes one tile. Its coordinate stage computes, one lane
 //    per visibility, the start cell and the oversample indices in float64
-//    (exact: the oversampling is a power of two) and stages them in LDS;
+//    (k = floor(c * os) of the float64 product: exact for power-of-two
+//    oversampling, the stated rounding for other factors); the results stay
+//    in the lane's registers and reach the whole wavefront through
+//    v_readlane;
+//  * when the tile's neighbourhoods fit the wavefront's LDS box, their
+//    subgrid cells are first copied there with loads that write LDS
+//    directly, and the gather reads LDS; otherwise it reads through the
+//    caches;
 //  * the gather maps the 64 lanes onto the 8 x 8 (t_v, t_u) taps. Each lane
 //    reads the 4 w values of its tap (32 contiguous bytes for complex64; one
 //    v-row of the neighbourhood is 256 contiguous bytes) and its G_uv weight
 //    (one coalesced 256-byte block per visibility). Loads go through buffer
 //    resources, so the hardware bounds check turns any offset outside the
-//    subgrid into zeros;
+//    subgrid into zeros. 16-bit storage with a G_w table of the same type
+//    sums over w with packed dot products;
 //  * eight visibilities are reduced across the wavefront together: two
 //    permlane swaps (lanes 32 apart, then 16 apart) and one DPP step halve the
 //    number of live partial sums at each level, then three DPP steps finish
 //    the 8-lane sums (Section 2 uses a warp reduction after a v-axis
 //    accumulation; here the reduction is shared between visibilities);
-//  * results are staged in LDS and written as one contiguous block per tile
-//    (Section 2 stages outputs in shared memory and writes them in bulk).
+//  * results are staged in LDS per tile, and each lane then writes its
+//    visibility's output at the visibility's own index (Section 2 stages
+//    outputs in shared memory and writes them in bulk).
 #include "dg_device.h"
 
 namespace dg {

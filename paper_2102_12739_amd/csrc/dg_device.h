@@ -235,8 +235,9 @@ __device__ __forceinline__ float load_gcf(const void* table, int64_t idx) {
 // ---------------------------------------------------------------------------
 
 // Start cell offset (first tap, inside its subgrid) and table positions of
-// visibility i. Per axis k = floor(c * os) in float64, which is exact for a
-// power-of-two os; the cell is k / os, the oversample index k mod os, and the
+// visibility i. Per axis k = floor(c * os) of the float64 product, which is
+// exact for a power-of-two os (for other factors this rounding is the
+// contract); the cell is k / os, the oversample index k mod os, and the
 // first tap sits W/2 - 1 cells below the cell. Returns false when the
 // neighbourhood leaves the subgrid or the coordinate is not finite.
 __device__ __forceinline__ bool coords_from(const Problem& pr, double u, double v, double w, int32_t& cell,

@@ -141,9 +141,10 @@ class Plan:
     """A degridding plan for one problem (owns the library's device scratch).
 
     ``offsets`` are the host CSR offsets ``[S+1]`` of the visibilities per
-    subgrid. Subgrids are ``[S, n_v, n_u, n_w]`` complex64, or
-    ``[S, n_v, n_u, n_w, 2]`` bfloat16 / float16 for the low-precision
-    storage dtypes.
+    subgrid. Subgrids are ``[S, n_v, n_u, n_w]`` complex64 (``grid_dtype``
+    "c64"), or ``[S, n_v, n_u, n_w, 2]`` bfloat16 / float16 ("cbf16" /
+    "cf16"). The tables ``G_uv [os_uv, os_uv, 8, 8]`` and ``G_w [os_w, 4]``
+    are float32, float16 or bfloat16 (``gcf_dtype`` "f32" / "f16" / "bf16").
     """
 
     def __init__(self, offsets, n_v: int = 512, n_u: int = 512, n_w: int = 4,
