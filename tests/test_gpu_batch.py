@@ -154,3 +154,38 @@ def test_batch_tuner_picks_a_candidate_and_keeps_results():
     for g, w in zip(got, want):
         assert np.array_equal(g, w)
     after.close()
+
+
+@pytest.mark.parametrize("grid_dtype,gcf_dtype", [("cbf16", "bf16"), ("cf16", "f16")])
+def test_batched_workload_16_bit_forms_full_size(grid_dtype, gcf_dtype):
+    """The batched workload (eight problems, os in {8, 16, 32}) stored in a
+    16-bit form whose w sums run on the packed dot products, tuned and
+    launched as one batch: every output against the oracle on the stored
+    inputs (float32 accumulation), and within the 16-bit bound of the FP32
+    inputs."""
+    from paper_2102_12739_amd.degrid import batch_tune
+    from tests.gpu_common import stored_reference_inputs
+    probs = wl.batched(seed=2)
+    announce(f"batch full {grid_dtype}/{gcf_dtype}")
+    ts = [upload(p, grid_dtype, gcf_dtype) for p in probs]
+    plans = [plan_for(p, grid_dtype=grid_dtype, gcf_dtype=gcf_dtype) for p in probs]
+    for pl, t in zip(plans, ts):
+        pl.sort(t["uvw"])
+    args = [(t["sub"], t["g_uv"], t["g_w"], t["uvw"]) for t in ts]
+    batch_tune(plans, args)
+    batch = Batch(plans)
+    outs = batch.execute(args)
+    torch.cuda.synchronize()
+    err = [0.0, 0.0]
+    for p, o in zip(probs, outs):
+        got = o.cpu().numpy()
+        sub, g_uv, g_w = stored_reference_inputs(p, grid_dtype, gcf_dtype)
+        ref_q, _ = oracle.degrid(sub, g_uv, g_w, p.uvw, p.offsets)
+        assert rel_l2(got, ref_q) <= REL_L2_FP32
+        ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+        err[0] += float(np.sum(np.abs(got - ref) ** 2))
+        err[1] += float(np.sum(np.abs(ref) ** 2))
+    # three bf16 roundings (storage, both tables), or fp16 ones
+    assert (err[0] / err[1]) ** 0.5 <= (3e-3 if grid_dtype == "cbf16" else 1e-3)
+    batch.close()
+    del ts
