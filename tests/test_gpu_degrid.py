@@ -302,3 +302,41 @@ def test_graph_captured_degrid_and_adjoint_replays_match_eager(sort):
         plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"])
         torch.cuda.synchronize()
     del g
+
+
+def test_largest_supported_subgrid():
+    """One subgrid of 4096 x 8184 x 4 complex64, just under the 1 GiB limit
+    per subgrid, so that byte offsets reach the top of the 32-bit buffer
+    offsets: visibilities spread over the whole subgrid plus the four
+    corners of the valid box and points just outside it, against the oracle
+    in input order and sorted, and the adjoint (atomic scatter: 8184 is not
+    a multiple of the owner block)."""
+    n_v, n_u = 4096, 8184
+    assert n_v * n_u * 4 * 8 < 1 << 30
+    p = wl.make_problem("largest", [12000], seed=27, kind="mixed", n_v=n_v, n_u=n_u)
+    box = wl.interior_box(n_v, n_u, 4)
+    eps = 1e-6
+    corners = [(box.lo[0], box.lo[1], box.lo[2]), (box.hi[0] - eps, box.hi[1] - eps, box.hi[2] - eps),
+               (box.lo[0], box.hi[1] - eps, box.lo[2]), (box.hi[0] - eps, box.lo[1], box.hi[2] - eps),
+               (box.hi[0], box.hi[1] - eps, box.lo[2]), (box.lo[0], box.hi[1], box.lo[2])]   # last two: just outside
+    p.uvw[:len(corners)] = np.array(corners)
+    announce(f"largest subgrid {n_v}x{n_u}x4, N={p.n_vis}")
+    t = upload(p)
+    plan = plan_for(p)
+    ref, oob = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert oob == 2
+    got = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    assert plan.oob_count() == 2
+    assert rel_l2(got, ref) <= REL_L2_FP32
+    assert np.all(got[4:6] == 0)
+    scale = float(np.max(np.abs(ref)))
+    assert np.max(np.abs(got[:4] - ref[:4])) <= 1e-5 * scale
+    plan.sort(t["uvw"])
+    got_s = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    assert np.array_equal(got_s, got)
+    vin = wl.complex_noise(27, p.n_vis, 1.0)
+    g = plan.adjoint(torch.from_numpy(vin).to(device()), t["g_uv"], t["g_w"], t["uvw"])
+    ref_g, _ = oracle.grid(vin, p.g_uv, p.g_w, p.uvw, p.offsets, plan.shape)
+    assert rel_l2(g.cpu().numpy(), ref_g) <= REL_L2_FP32
+    del t, g
+    torch.cuda.empty_cache()
