@@ -281,6 +281,12 @@ def main(argv=None):
                      "kernel": "degrid_kernel<c64,f32>", "bytes_per_vis": BYTES_PER_VIS["c64"],
                      "kernel_ms": ms_kernel},
     }
+    if traffic is not None:
+        # the rate at which bytes actually reach HBM (rocprofv3 counters of the
+        # same kernel source), beside the algorithmic rate above
+        traffic_gbs = traffic / (ms_kernel * 1e-3) / 1e9
+        result["roofline"]["traffic_gbs"] = traffic_gbs
+        result["roofline"]["traffic_frac"] = traffic_gbs / HBM_PEAK_GBS
     # Per-launch distribution, back to back (warm) and after writing 1 GiB
     # between launches (cold L2 and Infinity Cache), plus what the memory
     # system does on a plain copy and the bytes a launch cannot avoid.
