@@ -347,27 +347,34 @@ def main(argv=None):
         a64 = p.subgrids.astype(np.complex128)
         cores = len(os.sched_getaffinity(0))
         threads0 = oracle.num_threads()
-        runs = []
-        for _ in range(3):
+        # the whole workload, repeated for about 10 s (at least 3 runs)
+        runs, ref = [], None
+        while len(runs) < 3 or sum(runs) < 10.0:
             t = time.perf_counter()
             ref, _ = oracle.degrid(a64, p.g_uv, p.g_w, p.uvw, p.offsets)
             runs.append(time.perf_counter() - t)
-        cpu_s = sorted(runs)[1]
-        # one thread, on the first eight subgrids (about 1/8 of the work)
+        cpu_s = float(np.median(runs))
+        # one thread, on the first eight subgrids (about 1/8 of the work),
+        # repeated for about 5 s
         n8 = int(p.offsets[8])
         oracle.set_num_threads(1)
-        t = time.perf_counter()
-        oracle.degrid(a64[:8], p.g_uv, p.g_w, p.uvw[:n8], p.offsets[:9])
-        one_s = time.perf_counter() - t
+        one_runs = []
+        while not one_runs or sum(one_runs) < 5.0:
+            t = time.perf_counter()
+            oracle.degrid(a64[:8], p.g_uv, p.g_w, p.uvw[:n8], p.offsets[:9])
+            one_runs.append(time.perf_counter() - t)
+        one_s = float(np.median(one_runs))
         oracle.set_num_threads(threads0)
         got = out.cpu().numpy().astype(np.complex128)
         rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         result["cpu_baseline"] = {"value": p.n_vis / cpu_s, "unit": "visibilities/s",
                                   "cores": threads0, "kind": "oracle",
                                   "sample": f"the whole workload ({p.n_vis} visibilities), FP64 C oracle, "
-                                            f"median of 3 runs ({cpu_s:.3f} s) on {threads0} OpenMP threads",
+                                            f"median of {len(runs)} runs ({cpu_s:.3f} s each, {sum(runs):.1f} s in all) "
+                                            f"on {threads0} OpenMP threads",
                                   "one_thread_value": n8 / one_s,
-                                  "one_thread_sample": f"subgrids 0-7 ({n8} visibilities), one run of {one_s:.2f} s",
+                                  "one_thread_sample": f"subgrids 0-7 ({n8} visibilities), median of {len(one_runs)} runs "
+                                                       f"({one_s:.3f} s each)",
                                   "host_cores": cores, "cpu_model": cpu_model()}
         result["rel_l2"] = rel
         result["max_abs"] = float(np.max(np.abs(got - ref)))
