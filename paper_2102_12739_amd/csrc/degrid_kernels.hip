@@ -7,9 +7,11 @@
 // matrix cores:
 //
 //  * persistent workgroups drain a list of tiles (n_b consecutive
-//    visibilities of one subgrid) from per-XCD queues, stealing from the
-//    other queues when their own is empty (this replaces the launch grid of
-//    Eq. (1));
+//    visibilities of one subgrid) from per-XCD queues (this replaces the
+//    launch grid of Eq. (1)): most of each queue is dealt round-robin to the
+//    wavefronts that serve it, without atomics; the rest goes through the
+//    queue's atomic cursor, and a wavefront whose queue is empty steals
+//    from the others;
 //  * each wavefront takes one tile. Its coordinate stage computes, one lane
 //    per visibility, the start cell and the oversample indices in float64
 //    (k = floor(c * os) of the float64 product: exact for power-of-two
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
 
     const int lane = lane_id();
     const int wv = (int)(threadIdx.x / kWave);
-    QueueState st{xcc_id() % P.q.n_queues, 0};
+    TileClaims st = degrid_claims(P.q, P.deal, wv);
     uint32_t wave_oob = 0;
 
     // Tiles are taken ahead of need (to hide the queue atomics) only while
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
     const int waves_per_queue = ((int)gridDim.x * kWavesPerBlock + P.q.n_queues - 1) / P.q.n_queues;
     auto ahead_ok = [&](int tile) { return queue_end(P.q, st.q) - tile > waves_per_queue; };
 
-    int t = uniform(pop_tile(P.q, P.ctl, st));
+    int t = uniform(claim_tile(P.q, P.deal, P.ctl, st));
     while (t >= 0) {
     // current tile and its coordinates (in flight until the loop needs them)
     Tile tc{};
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
             w = uvw[3 * vis_c + 2];
         }
     }
-    int t_nxt = uniform(ahead_ok(t) ? pop_tile(P.q, P.ctl, st) : -1);
+    int t_nxt = uniform(ahead_ok(t) ? claim_tile(P.q, P.deal, P.ctl, st) : -1);
     // pop of the tile after t_nxt, sent during the previous tile
     bool pend = false;
     uint32_t raw = 0;
@@ -199,8 +201,8 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
         // (wave-uniform: both pops return a readfirstlane value; stated so
         // that the tile descriptors derived from it stay in scalar registers)
         const int t_after = uniform(!has_next ? -1
-                                              : (pend ? pop_resolve(P.q, P.ctl, st, raw)
-                                                      : (ahead_ok(t_nxt) ? pop_tile(P.q, P.ctl, st) : -1)));
+                                              : (pend ? claim_resolve(P.q, P.deal, P.ctl, st, raw)
+                                                      : (ahead_ok(t_nxt) ? claim_tile(P.q, P.deal, P.ctl, st) : -1)));
         pend = false;
         // the pop of the tile after next is sent during this tile (below)
         // only when that one is not among the queue's last tiles
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
             wave_lds_sync();
             // the pop of the tile after next travels while this tile is gathered
             if (send_ahead) {
-                raw = pop_issue(P.ctl, st);
+                raw = claim_issue(P.ctl, st);
                 pend = true;
             }
         }
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
         } else {
             gather_tile<G, F, NB, false, kPlane1, DEEP>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
             if (send_ahead) {
-                raw = pop_issue(P.ctl, st);
+                raw = claim_issue(P.ctl, st);
                 pend = true;
             }
         }
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
         w = wn;
     }
     // the look-ahead stopped (or the queues are empty): take the next tile now
-    t = uniform(pop_tile(P.q, P.ctl, st));
+    t = uniform(claim_tile(P.q, P.deal, P.ctl, st));
     }
     finish_launch(P.ctl, wave_oob);
 }
@@ -454,8 +456,10 @@ int degrid_variant_max_nb(int variant) {
     return (variant >= 0 && variant < kNumVariants) ? kVariants[variant].nb : -1;
 }
 
-hipError_t launch_degrid(const LaunchParams& p, int grid_kind, int gcf_kind, int variant,
+hipError_t launch_degrid(const LaunchParams& params, int grid_kind, int gcf_kind, int variant,
                          int blocks, hipStream_t stream) {
+    LaunchParams p = params;
+    p.deal = deal_static(p.q, blocks, kWavesPerBlock);
     switch (grid_kind * 3 + gcf_kind) {
         case kGridC64 * 3 + kGcfF32: return launch_degrid_v<kGridC64, kGcfF32>(p, variant, blocks, stream);
         case kGridC64 * 3 + kGcfF16: return launch_degrid_v<kGridC64, kGcfF16>(p, variant, blocks, stream);

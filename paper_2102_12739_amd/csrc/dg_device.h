@@ -83,22 +83,89 @@ __device__ __forceinline__ int queue_end(const QueueSpec& qs, int q) {
     return e;
 }
 
-// The two halves of a pop whose atomic is left in flight while the
-// wavefront works: pop_issue sends the cursor increment of the current queue
-// and returns without waiting; pop_resolve (called later) turns the returned
-// index into a tile, or, when that queue has run dry, carries on as pop_tile.
-__device__ __forceinline__ uint32_t pop_issue(Ctl* ctl, const QueueState& st) {
+// Tile claims of the degrid kernel. Every atomic on a queue cursor is served
+// one after another where the cursor lives (about 14 ns apiece when they
+// queue), so most tiles are dealt without one: the launch's static deal
+// (computed on the host for its grid size) gives most of each queue
+// round-robin to the wavefronts that serve it, and only the rest goes
+// through the cursor, one tile per atomic, with stealing as for pop_tile.
+// Round-robin dealing keeps the shares even where tile costs vary along the
+// queue.
+struct TileClaims {
+    int q;        // queue currently drained
+    int tried;    // queues found empty so far
+    int next;     // static share: tiles next, next + stride, ... below lim
+    int lim;
+    int stride;
+    int dbeg;     // first tile of queue q handed out by its cursor
+};
+
+// Workgroup b serves queue b mod n_queues: workgroups are placed on the XCDs
+// round-robin, so that is a queue of its own XCD. Without a static deal the
+// first claim goes straight to the cursor.
+__device__ __forceinline__ TileClaims degrid_claims(const QueueSpec& qs, const StaticDeal& d, int wv) {
+    TileClaims st;
+    st.q = uniform((int)blockIdx.x % qs.n_queues);
+    st.tried = 0;
+    st.next = 0;
+    st.lim = 0;
+    st.stride = 0;
+    if (d.on) {
+        st.next = uniform(qs.begin[st.q] + ((int)blockIdx.x / qs.n_queues) * kWavesPerBlock + wv);
+        st.lim = uniform(d.sbase[st.q]);
+        st.stride = uniform(d.stride[st.q]);
+    }
+    st.dbeg = uniform(d.sbase[st.q]);
+    return st;
+}
+
+// After the cursor of st.q ran dry: the next queue in rotation.
+__device__ __forceinline__ void next_queue(const QueueSpec& qs, const StaticDeal& d, TileClaims& st) {
+    st.q = (st.q + 1 == qs.n_queues) ? 0 : st.q + 1;
+    st.tried++;
+    st.dbeg = uniform(d.sbase[st.q]);
+}
+
+// Next tile for this wavefront, or -1 once every queue is empty (at most
+// n_queues cursor probes at the end).
+__device__ __forceinline__ int claim_tile(const QueueSpec& qs, const StaticDeal& d, Ctl* ctl, TileClaims& st) {
+    if (st.next < st.lim) {
+        const int t = st.next;
+        st.next += st.stride;
+        return t;
+    }
+    while (st.tried < qs.n_queues) {
+        uint32_t idx = 0;
+        if (lane_id() == 0) idx = atomicAdd(&ctl->cursor[st.q].v[0], 1u);
+        const int t = st.dbeg + uniform((int)idx);
+        if (t < qs.end[st.q]) return t;
+        next_queue(qs, d, st);
+    }
+    return -1;
+}
+
+// The two halves of a claim whose atomic is left in flight while the
+// wavefront works: claim_issue sends the cursor increment (none while the
+// static share lasts) and returns without waiting; claim_resolve, called
+// before any other claim, turns the result into a tile, or carries on as
+// claim_tile when that queue has run dry.
+constexpr uint32_t kStaticClaim = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t claim_issue(Ctl* ctl, const TileClaims& st) {
+    if (st.next < st.lim) return kStaticClaim;
     uint32_t idx = 0;
     if (lane_id() == 0) idx = atomicAdd(&ctl->cursor[st.q].v[0], 1u);
     return idx;
 }
 
-__device__ __forceinline__ int pop_resolve(const QueueSpec& qs, Ctl* ctl, QueueState& st, uint32_t idx) {
-    const int t = qs.begin[st.q] + uniform((int)idx);
+__device__ __forceinline__ int claim_resolve(const QueueSpec& qs, const StaticDeal& d, Ctl* ctl, TileClaims& st,
+                                             uint32_t idx) {
+    const uint32_t r = (uint32_t)uniform((int)idx);
+    if (r == kStaticClaim) return claim_tile(qs, d, ctl, st);
+    const int t = st.dbeg + (int)r;
     if (t < qs.end[st.q]) return t;
-    st.q = (st.q + 1 == qs.n_queues) ? 0 : st.q + 1;
-    st.tried++;
-    return pop_tile(qs, ctl, st);
+    next_queue(qs, d, st);
+    return claim_tile(qs, d, ctl, st);
 }
 
 // Adds this wavefront's out-of-range count; the last workgroup of the launch

@@ -60,6 +60,7 @@ struct LaunchParams {
     const uint32_t* tile_vis;   // [n_tiles][kMaxNb]: visibility index of each work item
     Ctl* ctl;
     QueueSpec q;
+    StaticDeal deal;            // filled by launch_degrid for its grid size
     // Residual mode (one problem only; v_obs == nullptr: plain degrid). The
     // output becomes v_obs - degrid and each tile stores the float64 sum of
     // |residual|^2 of its visibilities in tile_loss[t] (summed afterwards by

@@ -122,6 +122,22 @@ QueueSpec split_queues_weighted(const std::vector<int64_t>& weights) {
     return q;
 }
 
+StaticDeal deal_static(const QueueSpec& q, int blocks, int waves_per_block) {
+    StaticDeal d{};
+    const int nq = q.n_queues;
+    for (int k = 0; k < kMaxQueues; ++k) {
+        if (k >= nq) continue;
+        const int nb = blocks > k ? (blocks - k + nq - 1) / nq : 0;
+        const int w = nb * waves_per_block;
+        const int64_t size = (int64_t)q.end[k] - q.begin[k];
+        const int64_t base = (nb > 0 && size >= (int64_t)kMinTilesPerWave * w) ? size * kStaticEighths / 8 : 0;
+        d.sbase[k] = q.begin[k] + (int32_t)base;
+        d.stride[k] = w;
+        if (base > 0) d.on = 1;
+    }
+    return d;
+}
+
 QueueSpec split_queues(const std::vector<Tile>& tiles) {
     std::vector<int64_t> w(tiles.size());
     for (size_t i = 0; i < tiles.size(); ++i) w[i] = tiles[i].count;

@@ -76,4 +76,21 @@ QueueSpec split_queues(const std::vector<Tile>& tiles);
 // The same split for work items of the given weights.
 QueueSpec split_queues_weighted(const std::vector<int64_t>& weights);
 
+// Static deal of a persistent launch over queues q: workgroup b serves queue
+// b mod n_queues, and wavefront r of the workgroups serving a queue takes
+// its tiles begin + r, begin + r + stride, ... below sbase without an atomic;
+// tiles from sbase on go through the queue's cursor. A queue gets a static
+// part (kStaticEighths / 8 of its tiles) only when it holds at least
+// kMinTilesPerWave tiles per serving wavefront; otherwise sbase = begin.
+constexpr int kStaticEighths = 6;
+constexpr int kMinTilesPerWave = 4;
+
+struct StaticDeal {
+    int32_t on;                   // 1 when some queue has a static part
+    int32_t sbase[kMaxQueues];    // first tile of queue q handed out by its cursor
+    int32_t stride[kMaxQueues];   // wavefronts serving queue q
+};
+
+StaticDeal deal_static(const QueueSpec& q, int blocks, int waves_per_block);
+
 }  // namespace dg

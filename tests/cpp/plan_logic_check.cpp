@@ -3,6 +3,7 @@
 //   plan_logic_check <nb> <count>...                    fixed-size tiles
 //   plan_logic_check fitted <nb> <cap> <min_fit> <pad_to> <file> tiles cut to fit a box;
 //       <file>: line 1 = per-subgrid counts, line 2 = start word per visibility
+//   plan_logic_check deal <nb> <blocks> <count>...       static deal of a launch
 //   plan_logic_check blocks <n_v> <n_u> <block> <file> output-block lists;
 //       <file>: counts, start words, visibility index per work position
 #include "plan_logic.h"
@@ -30,6 +31,27 @@ static void print(const std::vector<dg::Tile>& tiles) {
 
 int main(int argc, char** argv) {
     if (argc < 2) return 2;
+    if (std::strcmp(argv[1], "deal") == 0) {
+        // deal <nb> <blocks> <count>...: queues of fixed-size tiles and the
+        // static deal of a launch of <blocks> workgroups
+        if (argc < 4) return 2;
+        const int nb = std::atoi(argv[2]), blocks = std::atoi(argv[3]);
+        std::vector<int64_t> off(1, 0);
+        for (int i = 4; i < argc; ++i) off.push_back(off.back() + std::atoll(argv[i]));
+        const auto tiles = dg::build_tiles((int64_t)off.size() - 1, off.data(), nb, 0);
+        const dg::QueueSpec q = dg::split_queues(tiles);
+        const dg::StaticDeal d = dg::deal_static(q, blocks, 4);
+        std::printf("{\"n_queues\": %d, \"on\": %d, \"begin\": [", q.n_queues, d.on);
+        for (int i = 0; i < q.n_queues; ++i) std::printf("%s%d", i ? ", " : "", q.begin[i]);
+        std::printf("], \"end\": [");
+        for (int i = 0; i < q.n_queues; ++i) std::printf("%s%d", i ? ", " : "", q.end[i]);
+        std::printf("], \"sbase\": [");
+        for (int i = 0; i < q.n_queues; ++i) std::printf("%s%d", i ? ", " : "", d.sbase[i]);
+        std::printf("], \"stride\": [");
+        for (int i = 0; i < q.n_queues; ++i) std::printf("%s%d", i ? ", " : "", d.stride[i]);
+        std::printf("]}\n");
+        return 0;
+    }
     if (std::strcmp(argv[1], "blocks") == 0) {
         if (argc != 6) return 2;
         const int n_v = std::atoi(argv[2]), n_u = std::atoi(argv[3]), block = std::atoi(argv[4]);

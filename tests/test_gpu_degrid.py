@@ -13,9 +13,12 @@ pytestmark = pytest.mark.gpu
 
 
 def _run(p, **plan_kw):
+    """One launch into an output filled with NaN first, so that a visibility
+    the launch never writes fails the comparison."""
     t = upload(p)
     plan = plan_for(p, **plan_kw)
-    vis = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"])
+    vis = torch.full((p.n_vis,), float("nan"), dtype=torch.complex64, device=device())
+    plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"], out=vis)
     torch.cuda.synchronize()
     return plan, vis.cpu().numpy()
 
