@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
 
     const int lane = lane_id();
     const int wv = (int)(threadIdx.x / kWave);
-    TileClaims st = degrid_claims(P.q, P.deal, wv);
+    TileClaims st = start_claims(P.q, P.deal, wv);
     uint32_t wave_oob = 0;
 
     // Tiles are taken ahead of need (to hide the queue atomics) only while

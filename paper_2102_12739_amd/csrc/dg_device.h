@@ -83,7 +83,7 @@ __device__ __forceinline__ int queue_end(const QueueSpec& qs, int q) {
     return e;
 }
 
-// Tile claims of the degrid kernel. Every atomic on a queue cursor is served
+// Tile claims of the degrid and owner-computes adjoint kernels. Every atomic on a queue cursor is served
 // one after another where the cursor lives (about 14 ns apiece when they
 // queue), so most tiles are dealt without one: the launch's static deal
 // (computed on the host for its grid size) gives most of each queue
@@ -103,7 +103,7 @@ struct TileClaims {
 // Workgroup b serves queue b mod n_queues: workgroups are placed on the XCDs
 // round-robin, so that is a queue of its own XCD. Without a static deal the
 // first claim goes straight to the cursor.
-__device__ __forceinline__ TileClaims degrid_claims(const QueueSpec& qs, const StaticDeal& d, int wv) {
+__device__ __forceinline__ TileClaims start_claims(const QueueSpec& qs, const StaticDeal& d, int wv) {
     TileClaims st;
     st.q = uniform((int)blockIdx.x % qs.n_queues);
     st.tried = 0;

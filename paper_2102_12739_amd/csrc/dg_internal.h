@@ -86,6 +86,7 @@ struct OwnerParams {
     const uint32_t* plan_start;    // first tap (y0 << 16 | x0) per visibility at plan time
     Ctl* ctl;
     QueueSpec q;
+    StaticDeal deal;               // filled by launch_grid_owner for its grid size
     int32_t accumulate;            // 1: add to grid_out, 0: overwrite
     int32_t nby, nbx;              // blocks per subgrid along v and u
 };

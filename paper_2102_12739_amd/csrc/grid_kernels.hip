@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
     const int lane = lane_id();
     const int wv = (int)(threadIdx.x / kWave);
     const int tv = lane >> 3, tu = lane & 7;
-    QueueState st{xcc_id() % P.q.n_queues, 0};
+    TileClaims st = start_claims(P.q, P.deal, wv);
     const Problem& pr = P.prob;
     const __amdgpu_buffer_rsrc_t rg = make_rsrc(pr.g_uv, pr.guv_bytes);
     const uint32_t lane_g = (uint32_t)lane * GcfTraits<F>::kBytes;
@@ -222,14 +222,14 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
     // holds more blocks than wavefronts per queue (else after the block)
     const int waves_per_queue = ((int)gridDim.x * kWavesPerBlock + P.q.n_queues - 1) / P.q.n_queues;
 
-    int t = uniform(pop_tile(P.q, P.ctl, st));
+    int t = uniform(claim_tile(P.q, P.deal, P.ctl, st));
     while (t >= 0) {
         const ConstOwnerBlockPtr pb = (ConstOwnerBlockPtr)uniform_u64((uint64_t)P.blocks) + t;
         const int64_t begin = pb->begin;
         const int count = pb->count;
         const int blk = pb->block;
         const bool ahead = queue_end(P.q, st.q) - t > waves_per_queue;
-        const int t_next = uniform(ahead ? pop_tile(P.q, P.ctl, st) : -1);
+        const int t_next = uniform(ahead ? claim_tile(P.q, P.deal, P.ctl, st) : -1);
         const int per_sub = P.nby * P.nbx;
         const int s = blk / per_sub;
         const int by = (blk - s * per_sub) / P.nbx;
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
                 *reinterpret_cast<const float4*>(box + row * kPitch + col * 4);
         }
         wave_lds_sync();
-        t = ahead ? t_next : uniform(pop_tile(P.q, P.ctl, st));
+        t = ahead ? t_next : uniform(claim_tile(P.q, P.deal, P.ctl, st));
     }
     finish_launch(P.ctl, 0u);
 }
@@ -446,7 +446,9 @@ hipError_t adjoint_kernel_occupancy(int gcf_kind, int variant, int* n) {
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_grid_owner(const OwnerParams& p, int gcf_kind, int blocks, hipStream_t stream) {
+hipError_t launch_grid_owner(const OwnerParams& params, int gcf_kind, int blocks, hipStream_t stream) {
+    OwnerParams p = params;
+    p.deal = deal_static(p.q, blocks, kWavesPerBlock);
     if (gcf_kind == kGcfF32)
         hipLaunchKernelGGL((grid_owner_kernel<kGcfF32>), dim3(blocks), dim3(kBlockThreads), 0, stream, p);
     else if (gcf_kind == kGcfF16)
