@@ -240,3 +240,29 @@ def test_adjoint_with_16_bit_tables_matches_oracle(gcf_dtype, sort):
     g_uv, g_w = wl.stored_tables(p, gcf_dtype)
     ref, _ = oracle.grid(v, g_uv, g_w, p.uvw, p.offsets, plan.shape)
     assert rel_l2(g.cpu().numpy(), ref) <= REL_L2_FP32
+
+
+def test_owner_adjoint_paper_scale_full_size():
+    """The owner-computes adjoint at paper scale (64 x 512x512x4, 3.17 M
+    visibilities of uneven counts), where its output blocks are mostly dealt
+    statically: into a grid filled with NaN first, so that a block the launch
+    never writes fails; two runs bitwise equal; against the oracle."""
+    p = wl.paper_scale(seed=1)
+    announce(f"owner adjoint paper scale N={p.n_vis}")
+    t = upload(p)
+    plan = plan_for(p)
+    plan.sort(t["uvw"])
+    v = wl.complex_noise(160, p.n_vis, 1.0)
+    vt = torch.from_numpy(v).to(device())
+    out = torch.full(plan.shape, float("nan"), dtype=torch.complex64, device=device())
+    plan.adjoint(vt, t["g_uv"], t["g_w"], t["uvw"], out=out)
+    g1 = out.cpu().numpy()
+    out.fill_(float("nan"))
+    plan.adjoint(vt, t["g_uv"], t["g_w"], t["uvw"], out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(g1, out.cpu().numpy())
+    del out, t
+    ref, oob = oracle.grid(v, p.g_uv, p.g_w, p.uvw, p.offsets, plan.shape)
+    assert np.all(np.isfinite(g1))
+    assert rel_l2(g1, ref) <= REL_L2_FP32
+    assert plan.oob_count() == oob == 0
