@@ -115,14 +115,22 @@ typedef struct {
 } dg_plan_info;
 
 /*
- * Build a plan for S = n_subgrids subgrids.
+ * Build a plan for S = n_subgrids subgrids (Section 2: the inputs are the
+ * subgrid stack, the two oversampled GCFs and, for each subgrid, its list of
+ * visibility coordinates; a thread block takes N_b visibilities of one
+ * subgrid, and Eq. (1) sizes the launch from the largest list; here the
+ * N_b-visibility tiles of every subgrid form one queue that a persistent
+ * launch drains).
  *   d            descriptor (host); copied.
  *   vis_offsets  host int64[S+1]; offsets[0] == 0, non-decreasing; copied.
  *   stream       stream used for the plan's own uploads (may be NULL).
  *   out          receives the plan; *out is set to NULL on failure.
  * Allocates device scratch on the current HIP device. Synchronises 'stream'.
  * Returns DG_ERR_INVALID_ARG for a bad descriptor or offsets,
- * DG_ERR_UNSUPPORTED for supports other than 8 x 8 and 4, DG_ERR_NOMEM or
+ * DG_ERR_UNSUPPORTED for supports other than 8 x 8 and 4, for a subgrid of
+ * 2^30 bytes or more, for n_u > 65543 or n_v > 65542 (first taps are
+ * packed into 16 bits per axis), for 2^32 or more visibilities, or for more
+ * than 2^31 - 1 tiles, DG_ERR_NOMEM or
  * DG_ERR_HIP when the device side cannot be set up. A plan for subgrids with
  * n_w != 4 uses the one kernel variant that reads taps starting at any w
  * (no LDS staging); degrid_plan_set_kernel refuses the others for it, and
@@ -188,8 +196,9 @@ dg_status degrid_residual(dg_plan p, const void* subgrids, const void* g_uv, con
                           const void* v_obs, void* res_out, double* loss_out, hipStream_t stream);
 
 /*
- * Adjoint of degrid_execute (gridding): scatters G_w * G_uv * V_i onto the
- * 8 x 8 x 4 neighbourhood of every in-range visibility.
+ * Adjoint of degrid_execute (gridding; the transpose of the weighted sum of
+ * Section 2, which the paper does not implement): scatters G_w * G_uv * V_i
+ * onto the 8 x 8 x 4 neighbourhood of every in-range visibility.
  *   vis          device complex float32 [N].
  *   subgrids_out device complex float32 [S][n_v][n_u][n_w] (always float32,
  *                whatever the plan's grid dtype).
@@ -208,8 +217,12 @@ dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void*
                        hipStream_t stream);
 
 /*
- * Out-of-range visibilities seen by the last degrid_execute or grid_adjoint of
- * this plan. Synchronises the stream of that call.
+ * Out-of-range visibilities seen by the last degrid_execute, degrid_residual
+ * or grid_adjoint of this plan: those whose 8 x 8 x 4 neighbourhood, starting
+ * at the point g of Section 2, does not lie inside the subgrid (the paper does
+ * not say what happens there; such a visibility's output is 0). 0 before the
+ * first call and after a call on a plan without visibilities. Synchronises
+ * the stream of the last call.
  */
 dg_status degrid_oob_count(dg_plan p, int64_t* count);
 
@@ -258,14 +271,19 @@ dg_status degrid_destroy(dg_plan p);
 
 /*
  * Batch several plans (independent problems with their own S, counts and
- * oversampling, same grid and gcf dtypes) into one persistent launch. The
+ * oversampling, same grid and gcf dtypes) into one persistent launch. (Section
+ * 2 warns that uneven visibility counts per subgrid leave most blocks of the
+ * Eq. (1) launch idle, and Section 3 measures throughput against the counts;
+ * one queue over the tiles of several problems keeps the device full.) The
  * plans must stay alive while the batch exists. Allocates the batch's tile
- * list, queue and per-problem argument table.
+ * list, queue and per-problem argument table. DG_ERR_UNSUPPORTED for more
+ * than 65535 plans or 2^31 - 1 tiles in all.
  */
 dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out);
 
 /*
- * Degrid every problem of the batch in one launch.
+ * Degrid every problem of the batch in one launch (Section 2's degridding of
+ * each problem, as degrid_execute).
  *   args  host array of 5*n pointers: for problem i,
  *         args[5i+0] subgrids, [5i+1] g_uv, [5i+2] g_w, [5i+3] uvw,
  *         [5i+4] vis_out (all device pointers, as in degrid_execute).

@@ -75,6 +75,12 @@ dg_status validate_desc(const dg_desc* d) {
     const double cells = (double)d->n_v * d->n_u * d->n_w;
     if (cells * 8.0 >= (double)kOutOfRange)
         return fail(DG_ERR_UNSUPPORTED, "one subgrid must be smaller than %u bytes", kOutOfRange);
+    // First taps travel packed as (y0 << 16 | x0) in the work-order and
+    // owner-computes plans, with 0xFFFFFFFF marking "out of range": x0 must
+    // fit 16 bits and y0 must stay below 0xFFFF.
+    if (d->n_u - kSupportUV > 0xFFFF || d->n_v - kSupportUV > 0xFFFE)
+        return fail(DG_ERR_UNSUPPORTED, "subgrid sides must be at most %d (u) and %d (v), got %d and %d",
+                    0xFFFF + kSupportUV, 0xFFFE + kSupportUV, d->n_u, d->n_v);
     return DG_OK;
 }
 
@@ -86,6 +92,9 @@ dg_status validate_offsets(int64_t n_sub, const int64_t* off) {
     for (int64_t s = 0; s < n_sub; ++s)
         if (off[s + 1] < off[s])
             return fail(DG_ERR_INVALID_ARG, "vis_offsets must be non-decreasing (at %lld)", (long long)s);
+    // visibility indices of work items and work orders are 32-bit
+    if (off[n_sub] > (int64_t)0xFFFFFFFF)
+        return fail(DG_ERR_UNSUPPORTED, "at most 2^32 - 1 visibilities per plan, got %lld", (long long)off[n_sub]);
     return DG_OK;
 }
 
@@ -371,6 +380,11 @@ constexpr int kBoxRowPad = 16;
 dg_status rebuild_tiles(dg_plan_* p, int32_t n_b_req, hipStream_t stream) {
     const int box = degrid_variant_box_bytes(p->variant);
     const int32_t n_b = std::min<int32_t>(n_b_req, degrid_variant_max_nb(p->variant));
+    int64_t plain_tiles = 0;   // tiles of n_b visibilities, before building any
+    for (int64_t s = 0; s < p->n_sub; ++s) plain_tiles += (p->offsets[s + 1] - p->offsets[s] + n_b - 1) / n_b;
+    if (plain_tiles > 0x7FFFFFFF)
+        return fail(DG_ERR_UNSUPPORTED, "%lld tiles: at most 2^31 - 1 per plan (use a larger n_b)",
+                    (long long)plain_tiles);
     std::vector<Tile> tiles;
     if (box > 0 && !p->start.empty()) {
         const int64_t cap = box / (int64_t)(grid_elem_bytes(p->desc.grid_dtype) * kSupportW);
@@ -379,6 +393,8 @@ dg_status rebuild_tiles(dg_plan_* p, int32_t n_b_req, hipStream_t stream) {
     } else {
         tiles = build_tiles(p->n_sub, p->offsets.data(), n_b, 0);
     }
+    if (tiles.size() > (size_t)0x7FFFFFFF)
+        return fail(DG_ERR_UNSUPPORTED, "%zu tiles: at most 2^31 - 1 per plan (use a larger n_b)", tiles.size());
     dg_status s = alloc_scratch(p->ds, tiles, {p->d_perm}, stream);
     if (s != DG_OK) return s;
     p->n_b_req = n_b_req;
@@ -493,7 +509,10 @@ dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_o
 dg_status degrid_execute(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w,
                          const double* uvw, void* vis_out, hipStream_t stream) {
     if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");
-    if (p->ds.n_tiles == 0) return DG_OK;   // no visibilities: nothing to write
+    if (p->ds.n_tiles == 0) {   // no visibilities: nothing to write, and nothing out of range
+        p->launched = false;
+        return DG_OK;
+    }
     if (!subgrids || !g_uv || !g_w || !uvw || !vis_out)
         return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
     if (dg_status s = check_alignment(p->desc, subgrids, g_uv, g_w, uvw, vis_out, nullptr, nullptr); s != DG_OK)
@@ -511,9 +530,10 @@ dg_status degrid_residual(dg_plan p, const void* subgrids, const void* g_uv, con
                           const void* v_obs, void* res_out, double* loss_out, hipStream_t stream) {
     if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");
     if (!loss_out) return fail(DG_ERR_INVALID_ARG, "loss_out is NULL");
-    if (p->ds.n_tiles == 0) {   // no visibilities: the loss is 0
+    if (p->ds.n_tiles == 0) {   // no visibilities: the loss is 0, and nothing is out of range
         hipError_t e = launch_set_f64(loss_out, 0.0, stream);
         if (e != hipSuccess) return hip_fail(e, "loss fill kernel launch");
+        p->launched = false;
         return DG_OK;
     }
     if (!subgrids || !g_uv || !g_w || !uvw || !v_obs || !res_out)
@@ -568,7 +588,10 @@ dg_status grid_adjoint(dg_plan p, const void* vis, const void* g_uv, const void*
         hipError_t e = launch_zero(subgrids_out, out_bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "zero-fill kernel launch");
     }
-    if (p->ds.n_tiles == 0) return DG_OK;
+    if (p->ds.n_tiles == 0) {   // nothing to add, and nothing out of range
+        p->launched = false;
+        return DG_OK;
+    }
     if (!vis || !g_uv || !g_w || !uvw) return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
     const Problem pr = problem_of(p, nullptr, g_uv, g_w, uvw, const_cast<void*>(vis), subgrids_out);
     hipError_t e = launch_grid_adjoint(params_for(p, pr), p->desc.gcf_dtype, p->variant, p->blocks_adj, stream);
@@ -803,6 +826,12 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
     const int max_nb = degrid_variant_max_nb(b->variant);
     std::vector<Tile> tiles;
     std::vector<const uint32_t*> perms;
+    size_t total_tiles = 0;
+    for (int32_t i = 0; i < n; ++i) total_tiles += plans[i]->tiles.size();
+    if (total_tiles > (size_t)0x7FFFFFFF) {
+        degrid_batch_destroy(b);
+        return fail(DG_ERR_UNSUPPORTED, "%zu tiles: at most 2^31 - 1 per batch", total_tiles);
+    }
     for (int32_t i = 0; i < n; ++i) {
         for (Tile t : plans[i]->tiles) {
             if (t.count > max_nb) {
@@ -882,7 +911,10 @@ dg_status degrid_batch_execute(dg_batch b, const void* const* args, hipStream_t 
     for (size_t i = 0; i < n; ++i)
         if (b->plans[i]->version != b->plan_versions[i])
             return fail(DG_ERR_NOT_READY, "plan %zu changed (sorted or tuned) after the batch was planned", i);
-    if (b->ds.n_tiles == 0) return DG_OK;
+    if (b->ds.n_tiles == 0) {   // no visibilities: nothing to write, and nothing out of range
+        b->launched = false;
+        return DG_OK;
+    }
     const bool same = b->uploaded && std::equal(b->last_args.begin(), b->last_args.end(), args);
     hipError_t e;
     if (!same) {

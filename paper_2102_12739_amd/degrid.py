@@ -429,7 +429,9 @@ def residual_loss(subgrids, g_uv, g_w, uvw, v_obs, plan: Plan) -> torch.Tensor:
 
 
 def degrid(subgrids, g_uv, g_w, uvw, offsets=None, plan: Plan | None = None, **plan_kw) -> torch.Tensor:
-    """Degrid with autograd support (differentiable with respect to ``subgrids``).
+    """Degrid with autograd support (differentiable with respect to
+    ``subgrids``, ``g_uv`` and ``g_w``: whichever of them require grad get
+    gradients through :class:`DegridFn`).
 
     A plan made here gets the plan-time work order of ``uvw`` (``Plan.sort``),
     which the gridding adjoint of the backward needs to run without global
@@ -440,7 +442,7 @@ def degrid(subgrids, g_uv, g_w, uvw, offsets=None, plan: Plan | None = None, **p
         s, n_v, n_u, n_w = subgrids.shape[:4]
         plan = Plan(offsets, n_v, n_u, n_w, os_uv=g_uv.shape[0], os_w=g_w.shape[0], **plan_kw)
         plan.sort(uvw)
-    if subgrids.requires_grad:
+    if torch.is_grad_enabled() and (subgrids.requires_grad or g_uv.requires_grad or g_w.requires_grad):
         return DegridFn.apply(subgrids, plan, g_uv, g_w, uvw)
     return plan.execute(subgrids, g_uv, g_w, uvw)
 

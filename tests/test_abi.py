@@ -87,6 +87,8 @@ def _desc(dg, **kw):
     (dict(n_b=65), 1), (dict(n_b=-1), 1), (dict(grid_dtype=3), 1), (dict(gcf_dtype=3), 1),
     (dict(n_v=7), 1), (dict(support_uv=6), 2), (dict(support_w=6), 2), (dict(n_w=3), 1),
     (dict(support_uv=0), 1), (dict(n_v=8192, n_u=8192), 2),
+    # first taps are packed into 16 bits per axis (0xFFFFFFFF means "none")
+    (dict(n_v=8, n_u=65544), 2), (dict(n_v=65543, n_u=8), 2),
 ])
 def test_invalid_descriptors_are_rejected_before_device_work(dg, kw, status):
     st, h = _plan_raw(dg, _desc(dg, **kw), [0, 10])
@@ -99,6 +101,26 @@ def test_invalid_descriptors_are_rejected_before_device_work(dg, kw, status):
 def test_invalid_offsets_are_rejected(dg, offsets, n_sub):
     st, h = _plan_raw(dg, _desc(dg), offsets, n_sub)
     assert st == 1 and h.value is None
+
+
+def test_largest_side_lengths_pass_validation(dg):
+    """The largest sides whose first taps still pack into 16 bits per axis
+    get past validation (they then fail only for want of a device here)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present: the plan would be built")
+    for kw in (dict(n_v=8, n_u=65543), dict(n_v=65542, n_u=8)):
+        st, h = _plan_raw(dg, _desc(dg, **kw), [0, 10])
+        assert st == 4 and h.value is None   # DG_ERR_HIP: no device
+
+
+@pytest.mark.parametrize("offsets", [[0, 1 << 32], [0, (1 << 31), (1 << 32) + 5]])
+def test_visibility_counts_of_2_to_the_32_are_refused(dg, offsets):
+    """Work items and work orders hold 32-bit visibility indices: a plan of
+    2^32 or more visibilities is refused before any device work."""
+    st, h = _plan_raw(dg, _desc(dg), offsets)
+    assert st == 2 and h.value is None
+    assert "2^32" in dg.lib().degrid_last_error().decode()
 
 
 def test_null_arguments(dg):
