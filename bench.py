@@ -8,10 +8,21 @@ each subgrid's list on a folded line with constant step in [0.05, 0.5] cells
 and the rest uniform in the subgrid (seed 1). Inputs are resident in HBM
 before timing starts. Prints one JSON line.
 
-The roofline object prices the degrid kernel against HBM bandwidth with the
-algorithmic bytes of each visibility: its 8 x 8 x 4 complex64 neighbourhood
-(2048 B), the 8 x 8 float32 G_uv block (256 B), 4 float32 G_w taps (16 B),
-float64 (u, v, w) (24 B) and the complex64 output (8 B): 2352 B.
+The headline value is the cold figure: every timed launch follows an
+untimed 1 GiB write that flushes the L2 and the Infinity Cache. The warm
+(back-to-back) figure is reported beside it.
+
+The roofline object prices the degrid kernel against three resources, each
+as a fraction of its peak that cannot exceed 1: HBM (the bytes rocprofv3's
+FETCH_SIZE and WRITE_SIZE counters measured for the same kernel source on
+the cold launches, and the compulsory bytes: every subgrid cell inside some
+in-range neighbourhood once, 32 B of coordinates and output per visibility,
+and both tables), LDS (bytes of the kernel's LDS instructions) and VALU
+issue (vector instructions). "bound" names the largest. The 2352 B per
+visibility of a neighbourhood read in full for every visibility (2048 B of
+subgrid, 256 B of G_uv, 16 B of G_w, 24 B of coordinates, 8 B of output) is
+reported only as an effective rate: neighbouring visibilities share most of
+their cells, which LDS and the caches serve, so that rate is not a roofline.
 """
 
 from __future__ import annotations
@@ -20,6 +31,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -28,14 +40,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# LDS: 256 bytes per clock per CU (CDNA4 doubles CDNA3's 128; a ds_read_b128
+# microbenchmark reached 196 B/clock/CU on this GPU), 256 CUs at 2.4 GHz.
+LDS_PEAK_GBS = 256 * 256 * 2.4
+# VALU issue: each of a CU's 4 SIMDs completes one wave64 instruction every
+# 4 clocks (16 lanes per clock without packed FP32), 256 CUs at 2.4 GHz, in
+# 1e9 wave instructions per second.
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters.json")
 BYTES_PER_VIS = {"c64": 2048 + 256 + 16 + 24 + 8, "cbf16": 1024 + 128 + 8 + 24 + 8, "cf16": 1024 + 128 + 8 + 24 + 8}
 # 16-bit forms of the same inputs: (storage, tables). fp16/fp16 and bf16/bf16
 # take the packed 16-bit dot products for the w sums; bf16 storage with fp16
 # tables widens both to float32.
 LOW_PRECISION_FORMS = (("cbf16", "f16"), ("cf16", "f16"), ("cbf16", "bf16"))
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "degrid_fp32_paper_scale_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_12739_amd", "csrc", f)
-                  for f in ("degrid_kernels.hip", "dg_device.h", "dg_internal.h")]
+LOW_PRECISION_REL_L2 = 3e-3   # error bound of the 16-bit storage forms against the FP64 oracle on FP32 inputs
 FLUSH_BYTES = 1 << 30     # written between launches of the cold-cache timing
 
 
@@ -43,26 +61,375 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    """sha256[:16] of the degrid kernel's source and the device code it includes."""
+_CSRC = os.path.join(ROOT, "paper_2102_12739_amd", "csrc")
+_COMMON_DEVICE = ("dg_device.h", "dg_internal.h", "plan_logic.h")
+# Source files of each profiled kernel (with the device code they include).
+LEG_SOURCES = {
+    "degrid": ("degrid_kernels.hip",) + _COMMON_DEVICE,
+    "adjoint": ("grid_kernels.hip",) + _COMMON_DEVICE,
+    "table_grad": ("table_grad_kernels.hip",) + _COMMON_DEVICE,
+}
+
+
+def source_hash(kind: str) -> str:
+    """sha256[:16] of a kernel's source and the device code it includes."""
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
-        with open(path, "rb") as f:
+    for name in LEG_SOURCES[kind]:
+        with open(os.path.join(_CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+def kernel_source_hash() -> str:
+    return source_hash("degrid")
+
+
+def committed_counters(leg: str):
+    """Per-dispatch counter means of a profiling leg (profiles/counters.json),
+    if they were taken on the current source of the leg's kernel; else None."""
     try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
+        with open(COUNTERS_FILE) as f:
+            c = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    entry = c.get("legs", {}).get(leg)
+    if not entry or entry.get("source_sha256_16") != source_hash(LEGS[leg]["source"]):
         return None
-    return t.get("hbm_bytes_per_launch")
+    return entry
+
+
+def measured_traffic():
+    """Cold HBM bytes per launch of the headline kernel from the committed
+    counters, or None when they are stale."""
+    e = committed_counters("degrid")
+    return None if e is None else e.get("hbm_bytes")
+
+
+# Profiling legs: one kernel's launches on one workload, for rocprofv3 runs
+# (bench.py --leg NAME). "kernels" are the name prefixes of the dispatches
+# that belong to the leg in a trace.
+LEGS = {
+    "degrid": dict(source="degrid", workload="paper", grid="c64", gcf="f32", op="degrid",
+                   kernels=("degrid_kernel",)),
+    "degrid_bf16": dict(source="degrid", workload="paper", grid="cbf16", gcf="bf16", op="degrid",
+                        kernels=("degrid_kernel",)),
+    "degrid_fp16": dict(source="degrid", workload="paper", grid="cf16", gcf="f16", op="degrid",
+                        kernels=("degrid_kernel",)),
+    "degrid_bf16_f16": dict(source="degrid", workload="paper", grid="cbf16", gcf="f16", op="degrid",
+                            kernels=("degrid_kernel",)),
+    "diff_degrid": dict(source="degrid", workload="diff", grid="c64", gcf="f32", op="degrid",
+                        kernels=("degrid_kernel",)),
+    "diff_owner_adjoint": dict(source="adjoint", workload="diff", grid="c64", gcf="f32", op="adjoint",
+                               kernels=("grid_owner_kernel", "grid_fixup_kernel")),
+    "diff_scatter_adjoint": dict(source="adjoint", workload="diff", grid="c64", gcf="f32", op="adjoint",
+                                 unsorted=True, kernels=("grid_adjoint_kernel", "zero_kernel")),
+    "diff_table_grad": dict(source="table_grad", workload="diff", grid="c64", gcf="f32", op="table_grad",
+                            kernels=("table_grad_kernel", "zero_f32_kernel")),
+    "latency": dict(source="degrid", workload="plain", grid="c64", gcf="f32", op="degrid",
+                    kernels=("degrid_kernel",)),
+}
+
+
+def run_leg(name, steps, warmup, cold, kernel=None, nb=None):
+    """Launch one profiling leg: warmup untimed launches, then steps launches
+    timed one by one with HIP events on the launch stream (each after a 1 GiB
+    flush when cold). Prints one JSON line."""
+    import torch
+    from paper_2102_12739_amd import workload as wl
+    from paper_2102_12739_amd.degrid import Plan
+    if name == "copy":
+        # calibration of the HBM byte counters: a plain copy of 1 GiB
+        a = torch.ones((1 << 30) // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        ms = launch_times(lambda: b.copy_(a), warmup + steps)[warmup:]
+        return {"leg": name, "bytes": 1 << 30, "launches": steps, "kernel_ms": percentiles(ms)}
+    leg = LEGS[name]
+    p = {"paper": lambda: wl.paper_scale(seed=1), "diff": lambda: wl.differentiation(seed=4),
+         "plain": lambda: wl.plain_line(seed=0)}[leg["workload"]]()
+    sub, g_uv, g_w, uvw = upload_inputs(p, leg["grid"], leg["gcf"])
+    plan = Plan(p.offsets, p.n_v, p.n_u, p.n_w, p.os_uv, p.os_w, grid_dtype=leg["grid"], gcf_dtype=leg["gcf"])
+    if not leg.get("unsorted"):
+        plan.sort(uvw)
+    if kernel is not None:
+        plan.set_kernel(kernel, nb or 0)
+    dev = uvw.device
+    if leg["op"] == "degrid":
+        out = torch.empty(p.n_vis, dtype=torch.complex64, device=dev)
+        fn = lambda: plan.execute(sub, g_uv, g_w, uvw, out=out)   # noqa: E731
+    else:
+        vin = torch.from_numpy(wl.complex_noise(5, p.n_vis, 1.0)).to(dev)
+        if leg["op"] == "adjoint":
+            gout = torch.empty(plan.shape, dtype=torch.complex64, device=dev)
+            fn = lambda: plan.adjoint(vin, g_uv, g_w, uvw, out=gout)   # noqa: E731
+        else:
+            tg_uv = torch.empty(g_uv.shape, dtype=torch.float32, device=dev)
+            tg_w = torch.empty(g_w.shape, dtype=torch.float32, device=dev)
+            fn = lambda: plan.table_grad(sub, g_uv, g_w, uvw, vin, out_uv=tg_uv, out_w=tg_w)   # noqa: E731
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    flush = None
+    if cold:
+        flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+        flush = lambda: flush_buf.fill_(1.0)   # noqa: E731
+    ms = launch_times(fn, steps, flush)
+    res = {"leg": name, "workload": p.name, "visibilities": p.n_vis, "cold": bool(cold), "launches": steps,
+           "kernel_ms": percentiles(ms), "kernel_ms_mean": float(sum(ms) / len(ms)),
+           "plan": plan.info(), "source_sha256_16": source_hash(leg["source"])}
+    log(f"leg {name}: {res['kernel_ms']['median'] * 1e3:.1f} us median over {steps} launches"
+        f" ({'cold' if cold else 'warm'})")
+    return res
+
+
+def _leg_of_kernel(leg, kernel_name):
+    """The prefix in LEGS[leg]["kernels"] that names this dispatch, or None."""
+    for k in LEGS[leg]["kernels"] if leg in LEGS else ("__amd_rocclr_copyBuffer",):
+        if re.search(r"(^|::|\s)" + re.escape(k) + r"($|<|\()", kernel_name):
+            return k
+    return None
+
+
+def summarize_pmc(root):
+    """Collect rocprofv3 runs of the profiling legs into profiles/counters.json
+    and profiles/counters.md.
+
+    root holds one folder per run, named LEG__PASS (LEG a profiling leg or
+    "copy", PASS "stats" for a --kernel-trace --stats run, else the counter
+    names of a --pmc run). Per kernel of a leg the first dispatch is dropped
+    (the untimed warmup) and the rest averaged. FETCH_SIZE and WRITE_SIZE are
+    scaled by what the same counters read for the 1 GiB plain copy of the
+    "copy" leg (read and write 1 GiB each)."""
+    import csv
+    import glob
+    per = {}   # (leg, kernel) -> {"counters": {name: [values]}, "durations_ns": [...]}
+    hashes = {}   # leg -> source hashes printed by its runs (bench.py --leg prints one JSON line)
+    for log_path in sorted(glob.glob(os.path.join(root, "*__*.log"))):
+        leg = os.path.basename(log_path).partition("__")[0]
+        with open(log_path) as f:
+            for line in f:
+                if line.startswith("{") and '"source_sha256_16"' in line:
+                    hashes.setdefault(leg, set()).add(json.loads(line)["source_sha256_16"])
+    for run in sorted(glob.glob(os.path.join(root, "*__*"))):
+        if not os.path.isdir(run):
+            continue
+        leg, _, pass_name = os.path.basename(run).partition("__")
+        for path in glob.glob(os.path.join(run, "**", "*.csv"), recursive=True):
+            base = os.path.basename(path)
+            with open(path, newline="") as f:
+                rows = list(csv.DictReader(f))
+            if base.endswith("counter_collection.csv"):
+                by_dispatch = {}
+                for r in rows:
+                    k = _leg_of_kernel(leg, r.get("Kernel_Name", ""))
+                    if k is None:
+                        continue
+                    d = by_dispatch.setdefault((k, int(r["Dispatch_Id"])), {})
+                    d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+                for (k, disp), vals in sorted(by_dispatch.items()):
+                    e = per.setdefault((leg, k), {"counters": {}, "durations_ns": [], "seen": {}})
+                    seen = e["seen"].setdefault(pass_name, 0)
+                    e["seen"][pass_name] = seen + 1
+                    if seen == 0:
+                        continue   # warmup dispatch
+                    for name, v in vals.items():
+                        e["counters"].setdefault(name, []).append(v)
+            elif base.endswith("kernel_trace.csv") and pass_name == "stats":
+                seen = {}
+                for r in sorted(rows, key=lambda r: int(r.get("Dispatch_Id", 0))):
+                    k = _leg_of_kernel(leg, r.get("Kernel_Name", ""))
+                    if k is None:
+                        continue
+                    seen[k] = seen.get(k, 0) + 1
+                    if seen[k] == 1:
+                        continue
+                    e = per.setdefault((leg, k), {"counters": {}, "durations_ns": [], "seen": {}})
+                    e["durations_ns"].append(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+    mean = lambda v: float(sum(v) / len(v)) if v else None   # noqa: E731
+    cal = per.get(("copy", "__amd_rocclr_copyBuffer"), {"counters": {}})["counters"]
+    gib_kib = (1 << 30) / 1024.0
+    fetch_scale = gib_kib / mean(cal["FETCH_SIZE"]) if cal.get("FETCH_SIZE") else None
+    write_scale = gib_kib / mean(cal["WRITE_SIZE"]) if cal.get("WRITE_SIZE") else None
+    out = {"calibration": {"copy_bytes": 1 << 30, "copy_FETCH_SIZE_kib": mean(cal.get("FETCH_SIZE", [])),
+                           "copy_WRITE_SIZE_kib": mean(cal.get("WRITE_SIZE", [])),
+                           "fetch_scale": fetch_scale, "write_scale": write_scale},
+           "legs": {}}
+    for (leg, k), e in sorted(per.items()):
+        if leg not in LEGS:
+            continue
+        c = {name: mean(v) for name, v in e["counters"].items()}
+        ke = {"counters": c, "dispatches": max((len(v) for v in e["counters"].values()), default=0),
+              "duration_us": (mean(e["durations_ns"]) or 0.0) / 1e3 or None}
+        if c.get("FETCH_SIZE") is not None and c.get("WRITE_SIZE") is not None and fetch_scale and write_scale:
+            ke["hbm_bytes"] = 1024.0 * (c["FETCH_SIZE"] * fetch_scale + c["WRITE_SIZE"] * write_scale)
+        # the kernel source the runs were made with (none, or several: stale)
+        h = hashes.get(leg, set())
+        le = out["legs"].setdefault(leg, {"source_sha256_16": next(iter(h)) if len(h) == 1 else None,
+                                          "kernels": {}})
+        le["kernels"][k] = ke
+    for leg, le in out["legs"].items():
+        ks = le["kernels"].values()
+        if all("hbm_bytes" in k for k in ks):
+            le["hbm_bytes"] = sum(k["hbm_bytes"] for k in ks)
+        if all(k.get("duration_us") for k in ks):
+            le["duration_us"] = sum(k["duration_us"] for k in ks)
+    from paper_2102_12739_amd import workload as wl
+    works = {"paper": lambda: wl.paper_scale(seed=1), "diff": lambda: wl.differentiation(seed=4),
+             "plain": lambda: wl.plain_line(seed=0)}
+    comp = {}
+    for leg, le in out["legs"].items():
+        w = LEGS[leg]["workload"]
+        elem = 8 if LEGS[leg]["grid"] == "c64" else 4
+        if (w, elem) not in comp:
+            pw = works[w]()
+            comp[(w, elem)] = (compulsory_bytes(pw, elem), pw.n_vis)
+        le["compulsory_bytes"], le["visibilities"] = comp[(w, elem)]
+    with open(COUNTERS_FILE, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    with open(COUNTERS_FILE[:-5] + ".md", "w") as f:
+        f.write(counters_markdown(out))
+    log(f"wrote {COUNTERS_FILE}: legs {sorted(out['legs'])}")
+    return out
+
+
+# rocprofv3 passes of every profiling leg (one process each; bench.py --leg
+# LEG --cold --steps 5 --warmup 1 after "--").
+PMC_PASSES = (
+    ("FETCH_SIZE",),
+    ("WRITE_SIZE", "TCC_HIT_sum", "TCC_MISS_sum"),
+    ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_LDS_LOAD_BANDWIDTH", "SQ_INSTS_LDS_STORE_BANDWIDTH",
+     "SQ_INSTS_SALU", "SQ_INSTS_SMEM", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR"),
+    ("VALUBusy", "LdsUtil", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_ANY",
+     "SQ_BUSY_CYCLES"),
+)
+
+
+def counters_markdown(out):
+    """The per-kernel table of profiles/counters.md."""
+    cal = out["calibration"]
+    lines = [
+        "# Per-kernel rocprofv3 counters of the profiling legs (cold launches)",
+        "",
+        "Every leg is `python3 bench.py --leg LEG --cold --steps 5 --warmup 1`: one kernel's launches on one",
+        "workload, each timed launch after an untimed 1 GiB write (L2 and Infinity Cache flushed). One",
+        "rocprofv3 process per pass; the untimed first launch of each kernel is dropped and the other five",
+        "averaged. Passes:",
+        "",
+        "```",
+        "rocprofv3 --kernel-trace --stats -d DIR/LEG__stats -o run --output-format csv -- "
+        "python3 bench.py --leg LEG --cold --steps 5 --warmup 1",
+    ]
+    for ps in PMC_PASSES:
+        lines.append(f"rocprofv3 --pmc {' '.join(ps)} -d DIR/LEG__{'_'.join(ps)} -o run --output-format csv -- "
+                     "python3 bench.py --leg LEG --cold --steps 5 --warmup 1")
+    lines += [
+        "rocprofv3 --pmc FETCH_SIZE -d DIR/copy__FETCH_SIZE -o run --output-format csv -- "
+        "python3 bench.py --leg copy --steps 3 --warmup 1   (and WRITE_SIZE)",
+        "python3 bench.py --summarize-pmc DIR",
+        "```",
+        "",
+        f"Calibration (1 GiB `__amd_rocclr_copyBuffer`): FETCH_SIZE {cal['copy_FETCH_SIZE_kib']} KiB -> read scale "
+        f"{cal['fetch_scale']}; WRITE_SIZE {cal['copy_WRITE_SIZE_kib']} KiB -> write scale {cal['write_scale']}.",
+        "",
+        "Peaks: HBM 8000 GB/s; LDS 256 B/clock/CU x 256 CUs x 2.4 GHz = 157 286 GB/s; VALU issue one wave64",
+        "instruction per 4 clocks per SIMD = 614.4 G/s. LDS bytes = 64 x (SQ_INSTS_LDS_LOAD_BANDWIDTH +",
+        "SQ_INSTS_LDS_STORE_BANDWIDTH). VALUBusy and LdsUtil are rocprofv3's derived percentages of GPU time.",
+        "",
+        "| leg | kernel | us | HBM MB | HBM frac | compulsory frac | B/vis HBM | L2 hit | LDS GB/s (frac) | "
+        "VALU Ginst/s (frac) | VALUBusy % | LdsUtil % | bank-conflict cycles | waves waiting % |",
+        "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|",
+    ]
+    for leg, le in sorted(out["legs"].items()):
+        n = le.get("visibilities") or 1
+        for k, ke in sorted(le["kernels"].items()):
+            c = ke["counters"]
+            us = ke.get("duration_us")
+            t = (us or 0) * 1e-6
+            f = lambda x, fmt: (fmt.format(x) if x is not None else "-")   # noqa: E731
+            hbm = ke.get("hbm_bytes")
+            hbm_frac = hbm / t / 1e9 / HBM_PEAK_GBS if hbm and t else None
+            comp_frac = (le["compulsory_bytes"] / (le["duration_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+                         if le.get("duration_us") and len(le["kernels"]) and k == sorted(le["kernels"])[0] else None)
+            hit = (c["TCC_HIT_sum"] / (c["TCC_HIT_sum"] + c["TCC_MISS_sum"])
+                   if c.get("TCC_HIT_sum") is not None and c.get("TCC_MISS_sum") else None)
+            lds_b = ((c.get("SQ_INSTS_LDS_LOAD_BANDWIDTH") or 0) + (c.get("SQ_INSTS_LDS_STORE_BANDWIDTH") or 0)) * 64
+            lds_gbs = lds_b / t / 1e9 if t and "SQ_INSTS_LDS_LOAD_BANDWIDTH" in c else None
+            valu = c["SQ_INSTS_VALU"] / t / 1e9 if t and c.get("SQ_INSTS_VALU") is not None else None
+            wait = (100.0 * c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"]
+                    if c.get("SQ_WAIT_INST_ANY") is not None and c.get("SQ_WAVE_CYCLES") else None)
+            lines.append(
+                f"| {leg} | {k} | {f(us, '{:.1f}')} | {f(hbm / 1e6 if hbm else None, '{:.1f}')} | "
+                f"{f(hbm_frac, '{:.3f}')} | {f(comp_frac, '{:.3f}')} | {f(hbm / n if hbm else None, '{:.0f}')} | "
+                f"{f(hit, '{:.3f}')} | "
+                f"{f(lds_gbs, '{:.0f}')} ({f(lds_gbs / LDS_PEAK_GBS if lds_gbs is not None else None, '{:.3f}')}) | "
+                f"{f(valu, '{:.1f}')} ({f(valu / VALU_PEAK_GINST if valu is not None else None, '{:.3f}')}) | "
+                f"{f(c.get('VALUBusy'), '{:.1f}')} | {f(c.get('LdsUtil'), '{:.1f}')} | "
+                f"{f(c.get('SQ_LDS_BANK_CONFLICT'), '{:.3g}')} | {f(wait, '{:.1f}')} |")
+    lines += ["", "Compulsory bytes per leg (host count): " + ", ".join(
+        f"{leg} {le['compulsory_bytes'] / 1e6:.1f} MB for {le['visibilities']} visibilities"
+        for leg, le in sorted(out["legs"].items())), ""]
+    return "\n".join(lines)
+
+
+def roofline_object(n_vis, bytes_per_vis, kernel_ms, comp_bytes, counters, kernel):
+    """Fractions of three peaks for one kernel launch of kernel_ms: HBM
+    (counter bytes and compulsory bytes), LDS (bytes of LDS instructions)
+    and VALU issue (vector instructions), each <= 1 by construction when the
+    counters were taken on the same (cold) launches. "bound" names the
+    largest; the top-level achieved / peak / frac are that resource's."""
+    t = kernel_ms * 1e-3
+    hbm = {"peak_gbs": HBM_PEAK_GBS, "compulsory_bytes": comp_bytes, "compulsory_gbs": comp_bytes / t / 1e9,
+           "compulsory_frac": comp_bytes / t / 1e9 / HBM_PEAK_GBS,
+           "compulsory_basis": "every subgrid cell inside some in-range neighbourhood once, 24 B of (u, v, w) "
+                               "and 8 B of output per visibility, both tables"}
+    fracs = {}
+    res = {"kernel": kernel, "kernel_ms": kernel_ms, "hbm": hbm,
+           "effective": {"bytes_per_vis": bytes_per_vis, "gbs": bytes_per_vis * n_vis / t / 1e9,
+                         "note": "every visibility's full neighbourhood, G_uv block, G_w row, coordinates and "
+                                 "output; neighbouring visibilities share most cells, served from LDS and the "
+                                 "caches, so this rate is not a roofline"}}
+    traffic = None
+    if counters is not None:
+        kc = counters["kernels"].get("degrid_kernel", {}).get("counters", {})
+        traffic = counters.get("hbm_bytes")
+        if traffic:
+            hbm["traffic_bytes"] = traffic
+            hbm["achieved_gbs"] = traffic / t / 1e9
+            hbm["frac"] = hbm["achieved_gbs"] / HBM_PEAK_GBS
+            hbm["bytes_per_vis"] = traffic / n_vis
+            fracs["hbm"] = hbm["frac"]
+        if kc.get("SQ_INSTS_LDS") is not None:
+            # every LDS instruction of this kernel moves at most 16 bytes per lane
+            lds_bytes = kc["SQ_INSTS_LDS"] * 64 * 16
+            res["lds"] = {"instructions": kc["SQ_INSTS_LDS"], "bytes_upper": lds_bytes,
+                          "achieved_gbs": lds_bytes / t / 1e9, "peak_gbs": LDS_PEAK_GBS,
+                          "frac": lds_bytes / t / 1e9 / LDS_PEAK_GBS,
+                          "basis": "SQ_INSTS_LDS x 64 lanes x 16 B (the widest LDS access of the kernel)"}
+            fracs["lds"] = res["lds"]["frac"]
+        if kc.get("SQ_INSTS_VALU") is not None:
+            gi = kc["SQ_INSTS_VALU"] / t / 1e9
+            res["valu"] = {"instructions": kc["SQ_INSTS_VALU"], "achieved_ginst_s": gi,
+                           "peak_ginst_s": VALU_PEAK_GINST, "frac": gi / VALU_PEAK_GINST,
+                           "basis": "wave64 VALU instructions, 4 clocks each on a 16-lane SIMD"}
+            fracs["valu"] = res["valu"]["frac"]
+        for k in ("SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "TCC_HIT_sum", "TCC_MISS_sum"):
+            if kc.get(k) is not None:
+                res.setdefault("counters", {})[k] = kc[k]
+        if kc.get("TCC_HIT_sum") and kc.get("TCC_MISS_sum"):
+            hbm["l2_hit_rate"] = kc["TCC_HIT_sum"] / (kc["TCC_HIT_sum"] + kc["TCC_MISS_sum"])
+    if not fracs:
+        # no counters for this kernel source: the compulsory bytes alone
+        fracs["hbm"] = hbm["compulsory_frac"]
+        hbm["frac"] = hbm["compulsory_frac"]
+        hbm["achieved_gbs"] = hbm["compulsory_gbs"]
+    bound = max(fracs, key=fracs.get)
+    top = {"hbm": (hbm["achieved_gbs"], HBM_PEAK_GBS, "GB/s"),
+           "lds": (res.get("lds", {}).get("achieved_gbs"), LDS_PEAK_GBS, "GB/s"),
+           "valu": (res.get("valu", {}).get("achieved_ginst_s"), VALU_PEAK_GINST, "Ginst/s")}[bound]
+    res.update({"bound": bound, "achieved": top[0], "peak": top[1], "unit": top[2], "frac": fracs[bound],
+                "traffic": traffic, "fracs": fracs})
+    return {k: res[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "fracs", "kernel",
+                                "kernel_ms", "hbm") + tuple(k for k in ("lds", "valu", "counters") if k in res)
+            + ("effective",)}
 
 
 def upload_inputs(p, grid_dtype="c64", gcf_dtype="f32"):
@@ -143,6 +510,15 @@ def launch_times(fn, n, flush=None):
     return out
 
 
+def cold_launches(fn, n):
+    """Durations (ms) of n launches, each after an untimed 1 GiB write."""
+    import torch
+    buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    ms = launch_times(fn, n, flush=lambda: buf.fill_(1.0))
+    del buf
+    return ms
+
+
 def copy_bandwidth(n_bytes=1 << 30, reps=10):
     """Device-to-device copy rate (read + write bytes per second) on this GPU."""
     import torch
@@ -210,7 +586,21 @@ def main(argv=None):
     ap.add_argument("--main-only", action="store_true",
                     help="only the timed steps of the sorted plan (for a profiler's per-kernel statistics): "
                          "no input-order run, per-launch distributions, storage variants, CPU baseline or patterns")
+    ap.add_argument("--leg", choices=sorted(LEGS) + ["copy"],
+                    help="instead of the benchmark: launch one kernel's profiling leg (for rocprofv3)")
+    ap.add_argument("--cold", action="store_true", help="with --leg: flush 1 GiB before every timed launch")
+    ap.add_argument("--kernel", type=int, default=None, help="with --leg: the gather kernel variant")
+    ap.add_argument("--nb", type=int, default=None, help="with --leg and --kernel: visibilities per tile")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="instead of the benchmark: read rocprofv3 counter runs of the legs under DIR "
+                         "(one folder per run, named LEG__PASS) and write profiles/counters.json and .md")
     args = ap.parse_args(argv)
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc)
+        return 0
+    if args.leg:
+        print(json.dumps(run_leg(args.leg, args.steps, args.warmup, args.cold, args.kernel, args.nb)), flush=True)
+        return 0
     if args.study:
         import torch  # noqa: F401
         print(json.dumps(bench_study(max(args.steps, 5), max(args.warmup, 2))), flush=True)
@@ -251,13 +641,25 @@ def main(argv=None):
         plan.tune(*inputs, out=out)
         tune_s = time.perf_counter() - t
     info = plan.info()
-    ms_step, ms_kernel = time_plan(plan, inputs, out, args.steps, args.warmup)
+    run = lambda: plan.execute(*inputs, out=out)   # noqa: E731
+    # warm: back-to-back launches (wall time and HIP events over the region)
+    ms_warm_step, ms_warm_kernel = time_plan(plan, inputs, out, args.steps, args.warmup)
+    # cold (the headline): each timed launch follows an untimed 1 GiB write
+    # that flushes the L2 and the Infinity Cache
+    flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    flush = lambda: flush_buf.fill_(1.0)   # noqa: E731
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cold_ms = launch_times(run, args.steps, flush=flush)
+    torch.cuda.synchronize()
+    cold_wall_s = time.perf_counter() - t0
+    ms_step = float(np.mean(cold_ms))
     value = p.n_vis / (ms_step * 1e-3)
-    bytes_launch = BYTES_PER_VIS["c64"] * p.n_vis
-    achieved = bytes_launch / (ms_kernel * 1e-3) / 1e9
-    traffic = measured_traffic()
-    log(f"fp32: {ms_step:.4f} ms/step, kernel {ms_kernel:.4f} ms, {value:.4g} vis/s, "
-        f"{achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.2%} of HBM peak)")
+    comp = compulsory_bytes(p, 8)
+    counters = committed_counters("degrid")
+    roof = roofline_object(p.n_vis, BYTES_PER_VIS["c64"], ms_step, comp, counters, "degrid_kernel<c64,f32>")
+    log(f"fp32: cold {ms_step:.4f} ms/launch ({value:.4g} vis/s), warm {ms_warm_step:.4f} ms/step; "
+        f"bound {roof['bound']} at {roof['frac']:.2%}")
 
     result = {
         "metric": "degridded visibilities/sec + HBM GB/s % peak (FP32 vs batched BF16) at rel-L2",
@@ -275,42 +677,27 @@ def main(argv=None):
         "config": {"workload": p.name, "subgrids": p.n_subgrids, "subgrid_shape": [p.n_v, p.n_u, p.n_w],
                    "visibilities": p.n_vis, "os_uv": p.os_uv, "os_w": p.os_w, "grid_dtype": "c64",
                    "gcf_dtype": "f32", "n_b": info["n_b"], "grid_blocks": info["grid_blocks"],
-                   "seed": 1},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "degrid_kernel<c64,f32>", "bytes_per_vis": BYTES_PER_VIS["c64"],
-                     "kernel_ms": ms_kernel},
+                   "kernel": info["kernel"], "seed": 1,
+                   "timing": "cold: each of the timed launches follows an untimed 1 GiB write (L2 and "
+                             "Infinity Cache flushed); ms_per_step is the mean HIP-event duration of the "
+                             "timed launches on the launch stream"},
+        "roofline": roof,
+        "timing": {"cold_kernel_ms": percentiles(cold_ms), "cold_region_wall_s": cold_wall_s,
+                   "warm_ms_per_step": ms_warm_step, "warm_kernel_ms_mean": ms_warm_kernel,
+                   "warm_value": p.n_vis / (ms_warm_step * 1e-3)},
     }
-    if traffic is not None:
-        # the rate at which bytes actually reach HBM (rocprofv3 counters of the
-        # same kernel source), beside the algorithmic rate above
-        traffic_gbs = traffic / (ms_kernel * 1e-3) / 1e9
-        result["roofline"]["traffic_gbs"] = traffic_gbs
-        result["roofline"]["traffic_frac"] = traffic_gbs / HBM_PEAK_GBS
-    # Per-launch distribution, back to back (warm) and after writing 1 GiB
-    # between launches (cold L2 and Infinity Cache), plus what the memory
-    # system does on a plain copy and the bytes a launch cannot avoid.
+    # Per-launch distribution back to back, the memory system's plain-copy rate
     if not args.main_only:
-        flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda:0")
-        run = lambda: plan.execute(*inputs, out=out)   # noqa: E731
-        warm = percentiles(launch_times(run, 50))
-        cold = percentiles(launch_times(run, 20, flush=lambda: flush_buf.fill_(1.0)))
         del flush_buf
         torch.cuda.empty_cache()
-        comp = compulsory_bytes(p, 8)
-        result["timing"] = {
-            "warm_kernel_ms": warm, "cold_kernel_ms": cold,
-            "warm_median_value": p.n_vis / (warm["median"] * 1e-3),
-            "cold_median_value": p.n_vis / (cold["median"] * 1e-3),
-            "cold_median_roofline_frac": bytes_launch / (cold["median"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        }
-        result["roofline"]["copy_gbs"] = copy_bandwidth()
-        result["roofline"]["compulsory_bytes_per_launch"] = comp
-        result["roofline"]["compulsory_gbs_cold"] = comp / (cold["median"] * 1e-3) / 1e9
+        warm = percentiles(launch_times(run, 50))
+        result["timing"]["warm_kernel_ms"] = warm
+        result["timing"]["warm_median_value"] = p.n_vis / (warm["median"] * 1e-3)
+        result["roofline"]["hbm"]["copy_gbs"] = copy_bandwidth()
         result["device"] = {"name": torch.cuda.get_device_name(0),
                             "compute_units": torch.cuda.get_device_properties(0).multi_processor_count}
-        log(f"warm median {warm['median']:.4f} ms, cold median {cold['median']:.4f} ms, "
-            f"copy {result['roofline']['copy_gbs']:.0f} GB/s, compulsory {comp / 1e9:.3f} GB/launch")
+        log(f"warm median {warm['median']:.4f} ms, copy {result['roofline']['hbm']['copy_gbs']:.0f} GB/s, "
+            f"compulsory {comp / 1e9:.3f} GB/launch")
     if tune_s is not None:
         result["config"]["tune_s"] = tune_s
     result["config"]["work_order"] = ("input order" if args.input_order else
@@ -319,8 +706,7 @@ def main(argv=None):
         result["config"]["plan_sort_s"] = sort_s
     if sort_s is not None and not args.main_only:
         result["input_order"] = {"value": p.n_vis / (ms_in_order * 1e-3), "ms_per_step": ms_in_order,
-                                 "kernel_ms": kms_in_order,
-                                 "achieved_gbs": bytes_launch / (kms_in_order * 1e-3) / 1e9}
+                                 "kernel_ms": kms_in_order, "note": "warm, back to back"}
 
     # Low-precision storage of the same inputs (complex bf16 / fp16 subgrids,
     # fp16 / bf16 tables, fp32 accumulation), each with the plan's default kernel.
@@ -333,14 +719,18 @@ def main(argv=None):
             if not args.input_order:
                 vplan.sort(vin[3])
             vout = torch.empty_like(out)
-            vms, vkms = time_plan(vplan, vin, vout, args.steps, args.warmup)
-            variants[key] = {"value": p.n_vis / (vms * 1e-3), "ms_per_step": vms, "kernel_ms": vkms,
+            vms_warm, _ = time_plan(vplan, vin, vout, args.steps, args.warmup)
+            vrun = lambda: vplan.execute(*vin, out=vout)   # noqa: E731
+            vms = float(np.mean(cold_launches(vrun, args.steps)))
+            variants[key] = {"value": p.n_vis / (vms * 1e-3), "ms_per_step": vms,
                              "speedup_vs_fp32": ms_step / vms, "grid_dtype": gdt, "gcf_dtype": tdt,
+                             "warm_ms_per_step": vms_warm, "warm_speedup_vs_fp32": ms_warm_step / vms_warm,
                              "kernel": vplan.info()["kernel"],
-                             "achieved_gbs": BYTES_PER_VIS[gdt] * p.n_vis / (vkms * 1e-3) / 1e9,
+                             "effective_gbs": BYTES_PER_VIS[gdt] * p.n_vis / (vms * 1e-3) / 1e9,
                              "out": vout}
             del vin
-            log(f"{key}: {vms:.4f} ms/step ({variants[key]['speedup_vs_fp32']:.2f}x fp32)")
+            log(f"{key}: cold {vms:.4f} ms ({variants[key]['speedup_vs_fp32']:.2f}x fp32), "
+                f"warm {vms_warm:.4f} ms ({variants[key]['warm_speedup_vs_fp32']:.2f}x)")
 
     if not args.no_cpu_baseline:
         import oracle
@@ -386,6 +776,7 @@ def main(argv=None):
             gv = v["out"].cpu().numpy().astype(np.complex128)
             v["rel_l2_vs_fp32_inputs"] = float(np.linalg.norm(gv - ref) / np.linalg.norm(ref))
             v["rel_l2_vs_stored_inputs"] = float(np.linalg.norm(gv - ref_q) / np.linalg.norm(ref_q))
+            v["error_budget_used"] = v["rel_l2_vs_fp32_inputs"] / LOW_PRECISION_REL_L2
     for v in variants.values():
         v.pop("out", None)
     if variants:
@@ -459,11 +850,13 @@ def bench_batched(steps, warmup, check):
     torch.cuda.empty_cache()
 
     # The same eight problems in 16-bit forms, one graph launch each: bf16
-    # storage with bf16 tables (the bf16 form; packed bf16 dot products) and
-    # fp16 storage with fp16 tables (packed fp16 dot products); fp32
-    # accumulation and fp64 index arithmetic in both.
+    # storage with bf16 tables (packed bf16 dot products), bf16 storage with
+    # fp16 tables (the precision configuration's table type; both widened to
+    # fp32) and fp16 storage with fp16 tables (packed fp16 dot products);
+    # fp32 accumulation and fp64 index arithmetic in all three.
     low_out = {}
-    for key, gdt, tdt in (("batch_graph_bf16", "cbf16", "bf16"), ("batch_graph_fp16", "cf16", "f16")):
+    for key, gdt, tdt in (("batch_graph_bf16", "cbf16", "bf16"), ("batch_graph_bf16_f16tables", "cbf16", "f16"),
+                          ("batch_graph_fp16", "cf16", "f16")):
         lins = [upload_inputs(p, gdt, tdt) for p in probs]
         lplans = []
         for p, i in zip(probs, lins):
@@ -520,9 +913,12 @@ def bench_batched(steps, warmup, check):
             for which in ("fp32_inputs", "stored_inputs"):
                 a = acc[f"{key}:{which}"]
                 res[key][f"rel_l2_vs_{which}"] = (a[0] / a[1]) ** 0.5
+            res[key]["error_budget_used"] = res[key]["rel_l2_vs_fp32_inputs"] / LOW_PRECISION_REL_L2
             res[key]["max_abs_vs_fp32_inputs"] = worst[key]
     log(f"batched: graph {res['batch_graph']['ms_per_step']:.3f} ms, separate {res['separate_launches']['ms_per_step']:.3f} ms, "
-        f"bf16 graph {res['batch_graph_bf16']['ms_per_step']:.3f} ms, fp16 graph {res['batch_graph_fp16']['ms_per_step']:.3f} ms")
+        f"bf16 graph {res['batch_graph_bf16']['ms_per_step']:.3f} ms, "
+        f"bf16/f16-tables graph {res['batch_graph_bf16_f16tables']['ms_per_step']:.3f} ms, "
+        f"fp16 graph {res['batch_graph_fp16']['ms_per_step']:.3f} ms")
     return res
 
 
@@ -721,8 +1117,12 @@ def bench_study(steps, warmup):
     sub = torch.from_numpy(base.subgrids).to(dev)
     g_uv = torch.from_numpy(base.g_uv).to(dev)
     g_w = torch.from_numpy(base.g_w).to(dev)
-    mappings = [("cache gather, n_b 1", 0, 1), ("cache gather, n_b 64", 0, 64),
-                ("LDS box 12 KiB, n_b 32", 2, 32), ("LDS box 16 KiB, n_b 64", 4, 64)]
+    # the tap-per-lane mapping (close to the paper's D4) through the caches
+    # and with LDS boxes, and the D1 mapping (two visibilities per
+    # wavefront, accumulation along v)
+    mappings = [("D4-like cache gather, n_b 1", 0, 1), ("D4-like cache gather, n_b 64", 0, 64),
+                ("D4-like LDS box 12 KiB, n_b 32", 2, 32), ("D4-like LDS box 16 KiB, n_b 64", 4, 64),
+                ("D1-like, n_b 32", 6, 32), ("D1-like, n_b 64", 6, 64)]
     rows = []
     for scenario in ("equal", "ramp"):
         for e in (8, 10, 12, 14, 16, 18, 20):

@@ -262,9 +262,8 @@ dg_status check_alignment(const dg_desc& d, const void* subgrids, const void* g_
     return DG_OK;
 }
 
-Problem problem_of(const dg_plan_* p, const void* subgrids, const void* g_uv, const void* g_w,
-                   const double* uvw, void* vis, void* grid_out) {
-    const dg_desc& d = p->desc;
+Problem problem_of_desc(const dg_desc& d, const uint32_t* perm, const void* subgrids, const void* g_uv,
+                        const void* g_w, const double* uvw, void* vis, void* grid_out) {
     Problem pr{};
     pr.subgrids = subgrids;
     pr.g_uv = g_uv;
@@ -272,7 +271,7 @@ Problem problem_of(const dg_plan_* p, const void* subgrids, const void* g_uv, co
     pr.uvw = uvw;
     pr.vis = vis;
     pr.grid_out = grid_out;
-    pr.perm = p->d_perm;
+    pr.perm = perm;
     pr.cells_per_sub = (int64_t)d.n_v * d.n_u * d.n_w;
     pr.n_v = d.n_v;
     pr.n_u = d.n_u;
@@ -288,6 +287,11 @@ Problem problem_of(const dg_plan_* p, const void* subgrids, const void* g_uv, co
     pr.hi_v = (double)(d.n_v - kSupportUV / 2);
     pr.hi_w = (double)(d.n_w - kSupportW / 2);
     return pr;
+}
+
+Problem problem_of(const dg_plan_* p, const void* subgrids, const void* g_uv, const void* g_w,
+                   const double* uvw, void* vis, void* grid_out) {
+    return problem_of_desc(p->desc, p->d_perm, subgrids, g_uv, g_w, uvw, vis, grid_out);
 }
 
 // Workgroups for a persistent launch over n_tiles tiles: enough to fill the
@@ -370,7 +374,7 @@ int32_t default_variant(const dg_desc& d) { return d.grid_dtype == DG_GRID_C64 ?
 // Subgrids with more w planes than the w support have taps that start at any
 // w: only the deep variant (no staging, one load per w value) reads them.
 bool deep_only(const dg_desc& d) { return d.n_w != kSupportW; }
-bool variant_allowed(const dg_desc& d, int v) { return !deep_only(d) || v == kDeepVariant; }
+bool variant_allowed(const dg_desc& d, int v) { return !deep_only(d) || degrid_variant_any_depth(v); }
 
 // Smallest tile worth staging when tiles are cut to fit the box.
 constexpr int kMinStagedTile = 16;
@@ -782,8 +786,8 @@ dg_status degrid_plan_set_kernel(dg_plan p, int32_t kernel, int32_t n_b, hipStre
         return fail(DG_ERR_INVALID_ARG, "kernel must be in [-1, %d), got %d", degrid_variant_count(), kernel);
     if (n_b < 0 || n_b > kMaxNb) return fail(DG_ERR_INVALID_ARG, "n_b must be in [0, %d], got %d", kMaxNb, n_b);
     if (kernel >= 0 && !variant_allowed(p->desc, kernel))
-        return fail(DG_ERR_UNSUPPORTED, "subgrids with %d w planes need kernel %d (got %d)", p->desc.n_w,
-                    kDeepVariant, kernel);
+        return fail(DG_ERR_UNSUPPORTED, "subgrids with %d w planes need kernel %d or %d (got %d)", p->desc.n_w,
+                    kDeepVariant, kD1Variant, kernel);
     if (kernel >= 0) p->variant = kernel;
     return rebuild_tiles(p, n_b > 0 ? n_b : p->n_b_req, stream);
 }
@@ -819,7 +823,7 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
     // has subgrids deeper than the w support
     b->variant = plans[0]->variant;
     for (int32_t i = 0; i < n; ++i)
-        if (deep_only(plans[i]->desc)) b->variant = kDeepVariant;
+        if (!variant_allowed(plans[i]->desc, b->variant)) b->variant = kDeepVariant;
     b->grid_dtype = plans[0]->desc.grid_dtype;
     b->gcf_dtype = plans[0]->desc.gcf_dtype;
     b->device = plans[0]->device;
@@ -972,7 +976,7 @@ dg_status degrid_batch_tune(const dg_plan* plans, int32_t n, const void* const* 
     bool any_deep = false;
     for (int32_t i = 0; i < n; ++i) any_deep = any_deep || deep_only(plans[i]->desc);
     for (int var = 0; var < degrid_variant_count() && st == DG_OK; ++var) {
-        if (any_deep && var != kDeepVariant) continue;
+        if (any_deep && !degrid_variant_any_depth(var)) continue;
         int32_t last_nb = -1;
         for (int32_t nb_req : kCandidates) {
             const int32_t nb = std::min<int32_t>(nb_req, degrid_variant_max_nb(var));

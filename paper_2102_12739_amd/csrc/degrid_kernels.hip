@@ -42,82 +42,145 @@
 namespace dg {
 namespace {
 
-// Subgrid values of eight visibilities, fetched ahead of their arithmetic so
-// that the loads of one group overlap the sums of the previous one.
+// ---------------------------------------------------------------------------
+// D1 lane mapping (Section 2, kernel D1)
+// ---------------------------------------------------------------------------
+//
+// The wavefront takes two visibilities at once, one per 32-lane half. Lane
+// (t_u, t_w) of a half (t_u = lane / 4 mod 8, t_w = lane mod 4) walks the 8
+// v-rows of its visibility's neighbourhood: each step reads one value (a
+// half reads one v-row, 8 u x 4 w values, contiguous in memory) and its
+// G_uv weight, and accumulates along v; the sum is then weighted by
+// G_w[o_w][t_w] and reduced over the half. Eight pairs (16 visibilities)
+// are reduced together.
+
+// One value per lane for each of the 8 v-rows of one visibility, its 8 G_uv
+// weights and its G_w tap.
 template <int G>
-struct Fetch8 {
-    uint32_t raw[8][GridTraits<G>::kWords];
+struct PairFetch {
+    uint32_t raw[kSupportUV][GridTraits<G>::kWords / kSupportW];
+    float g[kSupportUV];
+    float gw;
 };
 
-// Lane j holds the coordinate-stage results of visibility j: a_off (byte
-// offset of its first tap in the LDS box or in the subgrid) and ow (its G_w
-// row); v_readlane hands them to the whole wavefront.
-template <int G, bool STAGED, uint32_t PLANE1, bool DEEP>
-__device__ __forceinline__ void fetch8(Fetch8<G>& f, int g0, int a_off, __amdgpu_buffer_rsrc_t ra,
-                                       uint32_t lane_a, const char* box) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const uint32_t aj = (uint32_t)__builtin_amdgcn_readlane(a_off, g0 + k);
-        if constexpr (STAGED) {
-            lds_w4<G, PLANE1>(box, lane_a + aj, f.raw[k]);
-        } else if constexpr (DEEP) {
-            load_w4_narrow<G>(ra, lane_a + aj, f.raw[k]);
-        } else {
-            load_w4<G>(ra, lane_a + aj, f.raw[k]);
-        }
-    }
+// Lane-dependent selection: visibility j0 + (upper half) of a value that
+// lane j holds for visibility j.
+__device__ __forceinline__ int half_pick(int x, int j0, bool upper) {
+    const int a = __builtin_amdgcn_readlane(x, j0);
+    const int b = __builtin_amdgcn_readlane(x, j0 + 1);
+    return upper ? b : a;
 }
 
-// Weighted sums of visibilities g0 .. g0+7 from their fetched values; gv[k]
-// is this lane's G_uv weight of visibility g0 + k, and the G_w rows (lane j
-// holds the byte offset gw_off of visibility j's row) come through the
-// scalar cache. Results land in out[g0 .. g0+7].
 template <int G, int F>
-__device__ __forceinline__ void sum8(const Fetch8<G>& f, const float* gv, uint32_t gw_off, uint64_t g_w,
-                                     float2* out, int g0) {
-    const int lane = lane_id();
-    float pre[8], pim[8];
-    uint2 gwp[8];
-    if constexpr (kPackedDot<G, F>) {
-        // the eight rows' scalar loads go out together, ahead of the sums
+__device__ __forceinline__ void fetch_pair(PairFetch<G>& f, int j0, int count, int a_off, int g_off, int ow,
+                                           __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rg, const void* g_w,
+                                           uint32_t lane_a, uint32_t lane_g, uint32_t row_bytes, int tw) {
+    const bool upper = lane_id() >= 32;
+    const bool live = j0 + (upper ? 1 : 0) < count;
+    const uint32_t aj = live ? (uint32_t)half_pick(a_off, j0, upper) : kOutOfRange;
+    const uint32_t gj = (uint32_t)half_pick(g_off, j0, upper);
+    const int oj = half_pick(ow, j0, upper);
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            gwp[k] = load_gw_pairs(g_w, (uint32_t)__builtin_amdgcn_readlane((int)gw_off, g0 + k));
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        float sr, si;
-        if constexpr (kPackedDot<G, F>) {
-            wsum_packed<G>(f.raw[k], gwp[k], sr, si);
+    for (int tv = 0; tv < kSupportUV; ++tv) {
+        const uint32_t off = aj == kOutOfRange ? kOutOfRange : aj + (uint32_t)tv * row_bytes + lane_a;
+        if constexpr (G == kGridC64) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(ra, off, 0, 0);
+            f.raw[tv][0] = v[0];
+            f.raw[tv][1] = v[1];
         } else {
-            const float4 gw = load_gw_row<F>(g_w, (uint32_t)__builtin_amdgcn_readlane((int)gw_off, g0 + k));
-            float re[4], im[4];
-            widen_w4<G>(f.raw[k], re, im);
-            sr = gw.x * re[0] + gw.y * re[1] + gw.z * re[2] + gw.w * re[3];
-            si = gw.x * im[0] + gw.y * im[1] + gw.z * im[2] + gw.w * im[3];
+            f.raw[tv][0] = __builtin_amdgcn_raw_buffer_load_b32(ra, off, 0, 0);
         }
-        pre[k] = gv[k] * sr;
-        pim[k] = gv[k] * si;
+        f.g[tv] = load_gcf_rsrc<F>(rg, gj + lane_g + (uint32_t)(tv * kSupportUV) * GcfTraits<F>::kBytes);
     }
-    reduce8(pre);
-    reduce8(pim);
-    if ((lane & 7) == 0) out[g0 + (lane >> 3)] = make_float2(pre[0], pim[0]);
+    f.gw = load_gcf<F>(g_w, (int64_t)oj * kSupportW + tw);
 }
 
-// All visibilities of a tile, groups of eight in a two-stage pipeline.
-template <int G, int F, int NB, bool STAGED, uint32_t PLANE1, bool DEEP>
-__device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, int ow, const float* gv,
-                                            __amdgpu_buffer_rsrc_t ra, uint64_t g_w, uint32_t lane_a,
-                                            const char* box) {
-    const uint32_t gw_off = gw_row_offset<F>(ow);
-    Fetch8<G> buf[2];
-    fetch8<G, STAGED, PLANE1, DEEP>(buf[0], 0, a_off, ra, lane_a, box);
+// v-accumulated, G_w-weighted partial sum of this lane for its visibility.
+template <int G>
+__device__ __forceinline__ void sum_pair(const PairFetch<G>& f, float& re, float& im) {
+    float ar = 0.0f, ai = 0.0f;
 #pragma unroll
-    for (int g0 = 0; g0 < NB; g0 += 8) {
+    for (int tv = 0; tv < kSupportUV; ++tv) {
+        float r, i;
+        if constexpr (G == kGridC64) {
+            r = __uint_as_float(f.raw[tv][0]);
+            i = __uint_as_float(f.raw[tv][1]);
+        } else if constexpr (G == kGridCBF16) {
+            r = __uint_as_float(f.raw[tv][0] << 16);
+            i = __uint_as_float(f.raw[tv][0] & 0xFFFF0000u);
+        } else {
+            const __half2 h = __builtin_bit_cast(__half2, f.raw[tv][0]);
+            r = __low2float(h);
+            i = __high2float(h);
+        }
+        ar += f.g[tv] * r;
+        ai += f.g[tv] * i;
+    }
+    re = ar * f.gw;
+    im = ai * f.gw;
+}
+
+// In: p[k] = this lane's partial sum for pair k (k = 0..7; the lower half
+// holds visibility 2k, the upper half 2k + 1). Out: p[0] on lane l = the
+// sum over l's half for pair 4 * bit4 + 2 * bit3 + bit2 of l. A permlane16
+// swap pairs the two rows of each half (rows 0/2 keep pair k, rows 1/3 take
+// pair k + 4), then DPP steps halve the live values by lane bits 3 and 2
+// and finish over bits 1 and 0.
+__device__ __forceinline__ void reduce_pairs8(float (&p)[8]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = swap_add16(p[k], p[k + 4]);
+    const int lane = lane_id();
+    const bool b3 = (lane & 8) != 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float keep = b3 ? p[k + 2] : p[k];
+        const float give = b3 ? p[k] : p[k + 2];
+        p[k] = keep + dpp<kDppRowRor8>(give);
+    }
+    const bool b2 = (lane & 4) != 0;
+    const float keep = b2 ? p[1] : p[0];
+    const float give = b2 ? p[0] : p[1];
+    float s = keep + dpp<kDppRowHalfMirror>(give);
+    s += dpp<kDppQuadXor2>(s);
+    s += dpp<kDppQuadXor1>(s);
+    p[0] = s;
+}
+
+// All visibilities of a tile with the D1 mapping; results land in out[0 ..
+// count). a_off: byte offset of each visibility's first tap in its subgrid
+// (kOutOfRange when out of range), g_off: byte offset of its G_uv block,
+// ow: its G_w row (lane j holds visibility j's).
+template <int G, int F, int NB>
+__device__ __forceinline__ void gather_tile_d1(float2* out, int count, int a_off, int g_off, int ow,
+                                               __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rg,
+                                               const void* g_w, uint32_t row_bytes, int n_w) {
+    static_assert(NB % 16 == 0, "groups of 16 visibilities");
+    const int lane = lane_id();
+    const int tu = (lane >> 2) & 7, tw = lane & 3;
+    const uint32_t lane_a = (uint32_t)(tu * n_w + tw) * GridTraits<G>::kElemBytes;
+    const uint32_t lane_g = (uint32_t)tu * GcfTraits<F>::kBytes;
+    PairFetch<G> buf[2];
+    fetch_pair<G, F>(buf[0], 0, count, a_off, g_off, ow, ra, rg, g_w, lane_a, lane_g, row_bytes, tw);
+#pragma unroll
+    for (int g0 = 0; g0 < NB; g0 += 16) {
         if (g0 < count) {
-            if (g0 + 8 < NB && g0 + 8 < count)
-                fetch8<G, STAGED, PLANE1, DEEP>(buf[((g0 / 8) + 1) & 1], g0 + 8, a_off, ra, lane_a, box);
-            sum8<G, F>(buf[(g0 / 8) & 1], gv + g0, gw_off, g_w, out, g0);
+            float pre[8], pim[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int j0 = g0 + 2 * k;
+                const int nxt = j0 + 2;
+                if (nxt < NB && nxt < count)
+                    fetch_pair<G, F>(buf[(k + 1) & 1], nxt, count, a_off, g_off, ow, ra, rg, g_w, lane_a, lane_g,
+                                     row_bytes, tw);
+                sum_pair<G>(buf[k & 1], pre[k], pim[k]);
+            }
+            reduce_pairs8(pre);
+            reduce_pairs8(pim);
+            if ((lane & 3) == 0) {
+                const int k = ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+                const int j = g0 + 2 * k + (lane >> 5);
+                if (j < count) out[j] = make_float2(pre[0], pim[0]);
+            }
         }
     }
 }
@@ -136,10 +199,11 @@ __device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, i
 // few values moved to scratch cost), two otherwise.
 constexpr int degrid_min_blocks(int grid_kind, int box) { return (grid_kind != kGridC64 && box == 0) ? 3 : 2; }
 
-template <int G, int F, int BOX, int NB, bool DEEP>
+template <int G, int F, int BOX, int NB, bool DEEP, bool D1>
 __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degrid_kernel(LaunchParams P) {
     using GT = GridTraits<G>;
     static_assert(NB % 8 == 0 && NB <= kMaxNb, "tile size");
+    static_assert(!D1 || BOX == 0, "the D1 mapping gathers through the caches");
     constexpr int kBoxBytes = BOX > 0 ? BOX : 16;
     constexpr uint32_t kPlane1 = kBoxBytes / 2;   // complex64: w 2-3 of every slot
     __shared__ float2 s_out[kWavesPerBlock][NB];
@@ -219,9 +283,9 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
         // out-of-range visibility reads block 0: its sum is discarded, because
         // the output stage writes 0 for it.
         const int g_off = in_range ? tab * (int)GcfTraits<F>::kBytes : 0;
-        float gv[NB];
+        float gv[D1 ? 1 : NB];
 #pragma unroll
-        for (int g0 = 0; g0 < NB; g0 += 8) {
+        for (int g0 = 0; g0 < (D1 ? 0 : NB); g0 += 8) {
             if (g0 < count) {
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
@@ -300,7 +364,14 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
                                  : (in_range ? cell * (int)GT::kElemBytes : (int)kOutOfRange);
         const uint32_t lane_a = staged ? ((uint32_t)(lane >> 3) * bp + (lane & 7)) * 16u
                                        : (uint32_t)(((lane >> 3) * pr.n_u + (lane & 7)) * pr.n_w) * GT::kElemBytes;
-        if (staged) {
+        if constexpr (D1) {
+            gather_tile_d1<G, F, NB>(s_out[wv], count, a_off, g_off, ow, ra, rg, pr.g_w,
+                                     (uint32_t)pr.n_u * pr.n_w * GT::kElemBytes, pr.n_w);
+            if (send_ahead) {
+                raw = claim_issue(P.ctl, st);
+                pend = true;
+            }
+        } else if (staged) {
             gather_tile<G, F, NB, true, kPlane1, false>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
         } else {
             gather_tile<G, F, NB, false, kPlane1, DEEP>(s_out[wv], count, a_off, ow, gv, ra, g_w, lane_a, box);
@@ -409,7 +480,8 @@ __global__ void zero_kernel(float4* p, int64_t n) {
 
 template <int G, int F, int V>
 hipError_t launch_degrid_t(const LaunchParams& p, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((degrid_kernel<G, F, kVariants[V].box, kVariants[V].nb, kVariants[V].deep>), dim3(blocks),
+    hipLaunchKernelGGL((degrid_kernel<G, F, kVariants[V].box, kVariants[V].nb, kVariants[V].deep, kVariants[V].d1>),
+                       dim3(blocks),
                        dim3(kBlockThreads), 0, s, p);
     return hipGetLastError();
 }
@@ -417,7 +489,8 @@ hipError_t launch_degrid_t(const LaunchParams& p, int blocks, hipStream_t s) {
 template <int G, int F, int V>
 hipError_t occ_degrid_t(int* n) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        n, degrid_kernel<G, F, kVariants[V].box, kVariants[V].nb, kVariants[V].deep>, kBlockThreads, 0);
+        n, degrid_kernel<G, F, kVariants[V].box, kVariants[V].nb, kVariants[V].deep, kVariants[V].d1>, kBlockThreads,
+        0);
 }
 
 template <int G, int F>
@@ -429,6 +502,7 @@ hipError_t launch_degrid_v(const LaunchParams& p, int variant, int blocks, hipSt
         case 3: return launch_degrid_t<G, F, 3>(p, blocks, s);
         case 4: return launch_degrid_t<G, F, 4>(p, blocks, s);
         case 5: return launch_degrid_t<G, F, 5>(p, blocks, s);
+        case 6: return launch_degrid_t<G, F, 6>(p, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -442,6 +516,7 @@ hipError_t occ_degrid_v(int variant, int* n) {
         case 3: return occ_degrid_t<G, F, 3>(n);
         case 4: return occ_degrid_t<G, F, 4>(n);
         case 5: return occ_degrid_t<G, F, 5>(n);
+        case 6: return occ_degrid_t<G, F, 6>(n);
         default: return hipErrorInvalidValue;
     }
 }
@@ -454,6 +529,9 @@ int degrid_variant_box_bytes(int variant) {
 }
 int degrid_variant_max_nb(int variant) {
     return (variant >= 0 && variant < kNumVariants) ? kVariants[variant].nb : -1;
+}
+bool degrid_variant_any_depth(int variant) {
+    return variant >= 0 && variant < kNumVariants && (kVariants[variant].deep || kVariants[variant].d1);
 }
 
 hipError_t launch_degrid(const LaunchParams& params, int grid_kind, int gcf_kind, int variant,

@@ -604,13 +604,103 @@ __device__ __forceinline__ void lds_w4(const char* box, uint32_t off, uint32_t (
     }
 }
 
+// ---------------------------------------------------------------------------
+// Gather of a tile (degrid kernels)
+// ---------------------------------------------------------------------------
+
+// Subgrid values of eight visibilities, fetched ahead of their arithmetic so
+// that the loads of one group overlap the sums of the previous one.
+template <int G>
+struct Fetch8 {
+    uint32_t raw[8][GridTraits<G>::kWords];
+};
+
+// Lane j holds the coordinate-stage results of visibility j: a_off (byte
+// offset of its first tap in the LDS box or in the subgrid) and ow (its G_w
+// row); v_readlane hands them to the whole wavefront.
+template <int G, bool STAGED, uint32_t PLANE1, bool DEEP>
+__device__ __forceinline__ void fetch8(Fetch8<G>& f, int g0, int a_off, __amdgpu_buffer_rsrc_t ra,
+                                       uint32_t lane_a, const char* box) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t aj = (uint32_t)__builtin_amdgcn_readlane(a_off, g0 + k);
+        if constexpr (STAGED) {
+            lds_w4<G, PLANE1>(box, lane_a + aj, f.raw[k]);
+        } else if constexpr (DEEP) {
+            load_w4_narrow<G>(ra, lane_a + aj, f.raw[k]);
+        } else {
+            load_w4<G>(ra, lane_a + aj, f.raw[k]);
+        }
+    }
+}
+
+// Weighted sums of visibilities g0 .. g0+7 from their fetched values; gv[k]
+// is this lane's G_uv weight of visibility g0 + k, and the G_w rows (lane j
+// holds the byte offset gw_off of visibility j's row) come through the
+// scalar cache. Results land in out[g0 .. g0+7].
+template <int G, int F>
+__device__ __forceinline__ void sum8(const Fetch8<G>& f, const float* gv, uint32_t gw_off, uint64_t g_w,
+                                     float2* out, int g0) {
+    const int lane = lane_id();
+    float pre[8], pim[8];
+    uint2 gwp[8];
+    if constexpr (kPackedDot<G, F>) {
+        // the eight rows' scalar loads go out together, ahead of the sums
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            gwp[k] = load_gw_pairs(g_w, (uint32_t)__builtin_amdgcn_readlane((int)gw_off, g0 + k));
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        float sr, si;
+        if constexpr (kPackedDot<G, F>) {
+            wsum_packed<G>(f.raw[k], gwp[k], sr, si);
+        } else {
+            const float4 gw = load_gw_row<F>(g_w, (uint32_t)__builtin_amdgcn_readlane((int)gw_off, g0 + k));
+            float re[4], im[4];
+            widen_w4<G>(f.raw[k], re, im);
+            sr = gw.x * re[0] + gw.y * re[1] + gw.z * re[2] + gw.w * re[3];
+            si = gw.x * im[0] + gw.y * im[1] + gw.z * im[2] + gw.w * im[3];
+        }
+        pre[k] = gv[k] * sr;
+        pim[k] = gv[k] * si;
+    }
+    reduce8(pre);
+    reduce8(pim);
+    if ((lane & 7) == 0) out[g0 + (lane >> 3)] = make_float2(pre[0], pim[0]);
+}
+
+// All visibilities of a tile, groups of eight in a two-stage pipeline.
+template <int G, int F, int NB, bool STAGED, uint32_t PLANE1, bool DEEP>
+__device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, int ow, const float* gv,
+                                            __amdgpu_buffer_rsrc_t ra, uint64_t g_w, uint32_t lane_a,
+                                            const char* box) {
+    const uint32_t gw_off = gw_row_offset<F>(ow);
+    Fetch8<G> buf[2];
+    fetch8<G, STAGED, PLANE1, DEEP>(buf[0], 0, a_off, ra, lane_a, box);
+#pragma unroll
+    for (int g0 = 0; g0 < NB; g0 += 8) {
+        if (g0 < count) {
+            if (g0 + 8 < NB && g0 + 8 < count)
+                fetch8<G, STAGED, PLANE1, DEEP>(buf[((g0 / 8) + 1) & 1], g0 + 8, a_off, ra, lane_a, box);
+            sum8<G, F>(buf[(g0 / 8) & 1], gv + g0, gw_off, g_w, out, g0);
+        }
+    }
+}
+
 // Kernel variants: (LDS box per wavefront in bytes, largest tile, deep).
 // Box 0 gathers through the caches only. A deep variant reads the 4 w values
 // of a tap with loads of one value each (naturally aligned at any first w),
 // for subgrids with more w planes than the w support; it never stages.
-struct Variant { int box; int nb; bool deep; };
-constexpr Variant kVariants[] = {{0, 64, false},     {8192, 32, false},  {12288, 32, false},
-                                 {16384, 32, false}, {16384, 64, false}, {0, 64, true}};
+// A D1 variant maps the lanes as the paper's kernel D1 (two visibilities
+// per wavefront, lanes over a v-row's (t_u, t_w) values, accumulation along
+// v, then a reduction); it reads one value per lane, so it also takes
+// subgrids deeper than the w support, and never stages.
+struct Variant { int box; int nb; bool deep; bool d1; };
+constexpr Variant kVariants[] = {{0, 64, false, false},     {8192, 32, false, false},  {12288, 32, false, false},
+                                 {16384, 32, false, false}, {16384, 64, false, false}, {0, 64, true, false},
+                                 {0, 64, false, true}};
+static_assert(kVariants[kD1Variant].d1 && kVariants[kD1Variant].box == 0, "D1 variant index");
 static_assert(kVariants[kDeepVariant].deep && kVariants[kDeepVariant].box == 0, "deep variant index");
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

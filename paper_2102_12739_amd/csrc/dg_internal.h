@@ -115,6 +115,9 @@ hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t stream);
 // Index of the degrid kernel variant for subgrids deeper than the w support
 // (no staging; one load per w value).
 constexpr int kDeepVariant = 5;
+// Index of the variant with the lane mapping of the paper's kernel D1 (two
+// visibilities per wavefront, lanes over (t_u, t_w), accumulation along v).
+constexpr int kD1Variant = 6;
 // *loss = sum of tile_loss[0 .. n_tiles) in a fixed order (same bits every time).
 hipError_t launch_loss_sum(const double* tile_loss, int64_t n_tiles, double* loss, hipStream_t stream);
 // *p = v (one float64 written by a kernel, so that graphs may capture it).
@@ -151,6 +154,7 @@ int degrid_variant_count();
 int adjoint_variant_count();
 int degrid_variant_box_bytes(int variant);   // LDS staging bytes per wavefront (0: none)
 int degrid_variant_max_nb(int variant);      // largest tile the variant accepts
+bool degrid_variant_any_depth(int variant);  // reads subgrids with n_w > 4 (one load per w value)
 constexpr int kMaxVariants = 8;
 // Adds dL/dG_uv and dL/dG_w of every in-range visibility to p.grad_uv and
 // p.grad_w (float atomics). deep: subgrids with more w planes than the support.
@@ -162,5 +166,6 @@ void table_grad_shape(int os_uv, int os_w, bool want_uv, bool want_w, size_t max
                       size_t* lds_bytes);
 // p[0 .. n) = 0.0f (a kernel, so that graphs may capture it).
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t stream);
+
 
 }  // namespace dg

@@ -414,6 +414,7 @@ hipError_t launch_adjoint_v(const LaunchParams& p, int variant, int blocks, hipS
         case 3: return launch_adjoint_t<F, 3>(p, blocks, s);
         case 4: return launch_adjoint_t<F, 4>(p, blocks, s);
         case 5: return launch_adjoint_t<F, 5>(p, blocks, s);
+        case 6: return launch_adjoint_t<F, 6>(p, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -427,6 +428,7 @@ hipError_t occ_adjoint_v(int variant, int* n) {
         case 3: return occ_adjoint_t<F, 3>(n);
         case 4: return occ_adjoint_t<F, 4>(n);
         case 5: return occ_adjoint_t<F, 5>(n);
+        case 6: return occ_adjoint_t<F, 6>(n);
         default: return hipErrorInvalidValue;
     }
 }

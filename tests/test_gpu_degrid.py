@@ -11,6 +11,8 @@ from tests.gpu_common import REL_L2_FP32, announce, device, plan_for, rel_l2, st
 
 pytestmark = pytest.mark.gpu
 
+D1_KERNEL = 6   # the kernel variant with the lane mapping of the paper's kernel D1
+
 
 def _run(p, **plan_kw):
     """One launch into an output filled with NaN first, so that a visibility
@@ -237,9 +239,12 @@ def test_sorted_work_order_with_out_of_range_and_empty_subgrids():
 @pytest.mark.parametrize("grid_dtype,gcf_dtype", [("c64", "f32"), ("cbf16", "f16"), ("cf16", "f32"), ("cf16", "f16"),
                                                  ("cbf16", "bf16")])
 def test_every_kernel_variant_gives_the_same_outputs(grid_dtype, gcf_dtype):
-    """The variants differ only in where a tile's cells are read from (LDS copy
-    of the tile's bounding box, or the caches); each visibility's arithmetic is
-    the same, so outputs are bitwise equal, sorted or not, dense or sparse."""
+    """The variants with the tap-per-lane mapping differ only in where a
+    tile's cells are read from (LDS copy of the tile's bounding box, or the
+    caches); each visibility's arithmetic is the same, so their outputs are
+    bitwise equal, sorted or not, dense or sparse. The D1 variant sums in
+    another order (along v first): its outputs are bitwise equal among
+    themselves and match the oracle to the float32 bar."""
     p = wl.make_problem("variants", [6000, 40, 0, 3000, 1], seed=26, kind="mixed", n_v=80, n_u=112,
                         os_uv=8, os_w=16)
     p.uvw[7] = (np.nan, 1.0, 1.5)
@@ -247,7 +252,7 @@ def test_every_kernel_variant_gives_the_same_outputs(grid_dtype, gcf_dtype):
     plan = plan_for(p, grid_dtype=grid_dtype, gcf_dtype=gcf_dtype)
     n_var = plan.info()["n_kernels"]
     assert n_var >= 2
-    outs = []
+    outs, outs_d1 = [], []
     for sort in (False, True):
         if sort:
             plan.sort(t["uvw"])
@@ -255,14 +260,18 @@ def test_every_kernel_variant_gives_the_same_outputs(grid_dtype, gcf_dtype):
             for n_b in (64, 13):
                 plan.set_kernel(k, n_b)
                 assert plan.info()["kernel"] == k
-                outs.append(plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy())
+                o = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+                (outs_d1 if k == D1_KERNEL else outs).append(o)
                 assert plan.oob_count() == 1
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+    for o in outs_d1[1:]:
+        assert np.array_equal(o, outs_d1[0])
     sub, g_uv, g_w = stored_reference_inputs(p, grid_dtype, gcf_dtype)
     ref, _ = oracle.degrid(sub, g_uv, g_w, p.uvw, p.offsets)
     assert rel_l2(outs[0], ref) <= REL_L2_FP32
-    assert outs[0][7] == 0
+    assert rel_l2(outs_d1[0], ref) <= REL_L2_FP32
+    assert outs[0][7] == 0 and outs_d1[0][7] == 0
     with pytest.raises(Exception):
         plan.set_kernel(n_var, 0)
 

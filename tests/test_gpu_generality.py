@@ -9,11 +9,12 @@ import torch
 import oracle
 from paper_2102_12739_amd import workload as wl
 from paper_2102_12739_amd.degrid import Batch, DegridError
-from tests.gpu_common import REL_L2_FP32, announce, device, plan_for, rel_l2, upload
+from tests.gpu_common import REL_L2_FP32, announce, device, plan_for, rel_l2, stored_reference_inputs, upload
 
 pytestmark = pytest.mark.gpu
 
 DEEP_KERNEL = 5   # the kernel variant for subgrids deeper than the w support
+D1_KERNEL = 6     # the D1-mapping variant, which also reads deeper stacks
 
 
 def _edge_coords(rng, box, os_uv, os_w, n):
@@ -127,10 +128,28 @@ def test_deep_plans_refuse_staged_kernels_and_tune_within_the_deep_one():
         plan.set_kernel(4, 64)
     assert e.value.status == 2
     info = plan.tune(t["sub"], t["g_uv"], t["g_w"], t["uvw"])
-    assert info["kernel"] == DEEP_KERNEL
+    assert info["kernel"] in (DEEP_KERNEL, D1_KERNEL)
     got = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
     ref, _ = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
     assert rel_l2(got, ref) <= REL_L2_FP32
+
+
+@pytest.mark.parametrize("grid_dtype,gcf_dtype", [("c64", "f32"), ("cbf16", "bf16"), ("cf16", "f16")])
+@pytest.mark.parametrize("n_b", [64, 9])
+def test_d1_mapping_reads_deep_stacks(grid_dtype, gcf_dtype, n_b):
+    """The D1-mapping variant reads one w value per lane, so it takes
+    subgrids deeper than the w support; odd tile sizes leave the last pair
+    of a tile half empty."""
+    p = _problem("deep-d1", [1300, 0, 777], seed=96, n_v=40, n_u=48, n_w=9, os_uv=12, os_w=5, edges=100)
+    t = upload(p, grid_dtype, gcf_dtype)
+    plan = plan_for(p, grid_dtype=grid_dtype, gcf_dtype=gcf_dtype)
+    plan.set_kernel(D1_KERNEL, n_b)
+    assert plan.info()["kernel"] == D1_KERNEL
+    got = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    sub, g_uv, g_w = stored_reference_inputs(p, grid_dtype, gcf_dtype)
+    ref, oob = oracle.degrid(sub, g_uv, g_w, p.uvw, p.offsets)
+    assert rel_l2(got, ref) <= REL_L2_FP32
+    assert plan.oob_count() == oob
 
 
 def test_batch_of_a_deep_and_a_plain_problem():
