@@ -159,6 +159,33 @@ dg_status degrid_execute(dg_plan p, const void* subgrids, const void* g_uv, cons
                          const double* uvw, void* vis_out, hipStream_t stream);
 
 /*
+ * Degrid without a plan, allocating nothing: for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same operation, arguments and results as
+ * degrid_execute on a plan in input order (degrid_plan without
+ * degrid_plan_sort), with the plan's inputs passed directly:
+ *   d            descriptor (host), as for degrid_plan; n_b = 0 means 64.
+ *   n_subgrids   S, at most 16384.
+ *   vis_offsets  host int64[S+1], as for degrid_plan; copied (stream-ordered)
+ *                into the library's device scratch before the call returns.
+ *   subgrids, g_uv, g_w, uvw, vis_out  device arrays as for degrid_execute.
+ *   oob_count    device int64, or NULL: receives this call's out-of-range
+ *                count (written by the call's kernels, stream-ordered).
+ * The scratch (a tile cursor and count, the offsets and per-subgrid tile
+ * offsets: 262 656 bytes) is one static device array per GPU, held until the
+ * process ends and shared by every call on that GPU: calls that overlap on
+ * one GPU (two streams, or two host threads) race and give wrong results.
+ * Calls no hipMalloc or hipFree. Every visibility's result equals
+ * degrid_execute's (input-order tiles of n_b visibilities, gathered through
+ * the caches). DG_ERR_UNSUPPORTED for more than 16384 subgrids or 2^31 - 1
+ * tiles; other argument errors as for degrid_plan and degrid_execute, all
+ * detected before any device work. Asynchronous on 'stream'.
+ */
+dg_status degrid_execute_noalloc(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_offsets,
+                                 const void* subgrids, const void* g_uv, const void* g_w, const double* uvw,
+                                 void* vis_out, int64_t* oob_count, hipStream_t stream);
+
+/*
  * Gradients with respect to the tables (the chain rule through the weighted
  * sum of Section 2; each visibility is linear in each table). Given the
  * gradient of a real loss L with respect to the visibilities,

@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libdegrid.so")
 SOURCES = [os.path.join(CSRC, "degrid_kernels.hip"), os.path.join(CSRC, "grid_kernels.hip"),
            os.path.join(CSRC, "degrid_api.cpp"),
            os.path.join(CSRC, "plan_logic.cpp"), os.path.join(CSRC, "plan_sort.hip"),
-           os.path.join(CSRC, "table_grad_kernels.hip")]
+           os.path.join(CSRC, "table_grad_kernels.hip"), os.path.join(CSRC, "noalloc.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Device code: gfx950 only; packed FP32 instructions disabled; hardware float

@@ -530,6 +530,34 @@ dg_status degrid_execute(dg_plan p, const void* subgrids, const void* g_uv, cons
     return DG_OK;
 }
 
+dg_status degrid_execute_noalloc(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_offsets,
+                                 const void* subgrids, const void* g_uv, const void* g_w, const double* uvw,
+                                 void* vis_out, int64_t* oob_count, hipStream_t stream) {
+    dg_status s = validate_desc(d);
+    if (s != DG_OK) return s;
+    if (n_subgrids > kNoAllocMaxSubgrids)
+        return fail(DG_ERR_UNSUPPORTED, "degrid_execute_noalloc takes at most %lld subgrids (its static scratch "
+                    "holds %lld offsets), got %lld", (long long)kNoAllocMaxSubgrids,
+                    (long long)kNoAllocMaxSubgrids + 1, (long long)n_subgrids);
+    s = validate_offsets(n_subgrids, vis_offsets);
+    if (s != DG_OK) return s;
+    const int64_t n = vis_offsets[n_subgrids];
+    if (n > 0 && (!subgrids || !g_uv || !g_w || !uvw || !vis_out))
+        return fail(DG_ERR_INVALID_ARG, "a device pointer is NULL");
+    if (s = check_alignment(*d, subgrids, g_uv, g_w, uvw, vis_out, nullptr, nullptr); s != DG_OK) return s;
+    if (reinterpret_cast<uintptr_t>(oob_count) % 8 != 0) return fail(DG_ERR_INVALID_ARG, "oob_count must be 8-byte aligned");
+    const int nb = d->n_b > 0 ? d->n_b : kMaxNb;
+    int64_t n_tiles = 0;
+    for (int64_t k = 0; k < n_subgrids; ++k) n_tiles += (vis_offsets[k + 1] - vis_offsets[k] + nb - 1) / nb;
+    if (n_tiles > 0x7FFFFFFF)
+        return fail(DG_ERR_UNSUPPORTED, "%lld tiles: at most 2^31 - 1 (use a larger n_b)", (long long)n_tiles);
+    const Problem pr = problem_of_desc(*d, nullptr, subgrids, g_uv, g_w, uvw, vis_out, nullptr);
+    const hipError_t e = launch_degrid_noalloc(pr, d->grid_dtype, d->gcf_dtype, deep_only(*d), vis_offsets, n_subgrids,
+                                               nb, n_tiles, reinterpret_cast<unsigned long long*>(oob_count), stream);
+    if (e != hipSuccess) return hip_fail(e, "degrid_execute_noalloc launch");
+    return DG_OK;
+}
+
 dg_status degrid_residual(dg_plan p, const void* subgrids, const void* g_uv, const void* g_w, const double* uvw,
                           const void* v_obs, void* res_out, double* loss_out, hipStream_t stream) {
     if (!p) return fail(DG_ERR_INVALID_ARG, "plan is NULL");

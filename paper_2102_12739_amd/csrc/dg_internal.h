@@ -167,5 +167,17 @@ void table_grad_shape(int os_uv, int os_w, bool want_uv, bool want_w, size_t max
 // p[0 .. n) = 0.0f (a kernel, so that graphs may capture it).
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t stream);
 
+// Degridding without a plan (defined in noalloc.hip): its scratch is a
+// file-scope device array of kNoAllocBytes per GPU (tile cursor and count,
+// the staged offsets and the tile offsets of at most kNoAllocMaxSubgrids
+// subgrids). Input-order tiles of nb visibilities; n_tiles = sum over
+// subgrids of ceil(N_s / nb). offsets_host [n_sub + 1] is copied into the
+// scratch on 'stream'. oob_out (device, may be null) receives the launch's
+// out-of-range count. Allocates nothing.
+constexpr int64_t kNoAllocMaxSubgrids = 16384;
+constexpr size_t kNoAllocBytes = 262656;   // 256 + 2 * 8 * (kNoAllocMaxSubgrids + 1), rounded up to 256
+hipError_t launch_degrid_noalloc(const Problem& pr, int grid_kind, int gcf_kind, bool deep,
+                                 const int64_t* offsets_host, int64_t n_sub, int nb, int64_t n_tiles,
+                                 unsigned long long* oob_out, hipStream_t stream);
 
 }  // namespace dg

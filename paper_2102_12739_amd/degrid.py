@@ -74,6 +74,8 @@ def lib():
         "degrid_plan": ([ctypes.POINTER(DgDesc), i64, ctypes.POINTER(ctypes.c_int64), vp,
                          ctypes.POINTER(vp)], i32),
         "degrid_execute": ([vp, vp, vp, vp, vp, vp, vp], i32),
+        "degrid_execute_noalloc": ([ctypes.POINTER(DgDesc), i64, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp,
+                                    vp, vp, vp], i32),
         "degrid_residual": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "grid_adjoint": ([vp, vp, vp, vp, vp, vp, i32, vp], i32),
         "degrid_table_grad": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
@@ -303,6 +305,37 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def degrid_noalloc(subgrids, g_uv, g_w, uvw, offsets, out=None, oob_count=None, grid_dtype: str = "c64",
+                   gcf_dtype: str = "f32", n_b: int = 0, stream=None) -> torch.Tensor:
+    """Degrid without a plan through ``degrid_execute_noalloc`` (the library
+    allocates nothing; its scratch is a static per-GPU array, so calls that
+    overlap on one GPU race). Shapes and dtypes as for :meth:`Plan.execute`;
+    ``offsets`` are the host CSR offsets ``[S+1]``. ``oob_count``, if given,
+    is a device int64 0-dim tensor that receives the out-of-range count."""
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    s = off.size - 1
+    shape = tuple(subgrids.shape[:4])
+    if shape[0] != s:
+        raise ValueError(f"subgrids hold {shape[0]} subgrids, offsets describe {s}")
+    n_v, n_u, n_w = shape[1:4]
+    grid_shape = shape if grid_dtype == "c64" else shape + (2,)
+    ps = _ptr(subgrids, "subgrids", _grid_tensor_dtype(grid_dtype), grid_shape)
+    tdt = _gcf_tensor_dtype(gcf_dtype)
+    pg = _ptr(g_uv, "g_uv", tdt)
+    pw = _ptr(g_w, "g_w", tdt)
+    os_uv, os_w = g_uv.shape[0], g_w.shape[0]
+    n = int(off[-1])
+    pu = _ptr(uvw, "uvw", torch.float64, (n, 3))
+    if out is None:
+        out = torch.empty(n, dtype=torch.complex64, device=uvw.device)
+    po = _ptr(out, "out", torch.complex64, (n,))
+    pc = _ptr(oob_count, "oob_count", torch.int64, ()) if oob_count is not None else None
+    d = DgDesc(n_v, n_u, n_w, 8, 4, os_uv, os_w, GRID_DTYPES[grid_dtype], GCF_DTYPES[gcf_dtype], n_b, 0)
+    _check(lib().degrid_execute_noalloc(ctypes.byref(d), s, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        ps, pg, pw, pu, po, pc, _stream_handle(stream)), "degrid_execute_noalloc")
+    return out
 
 
 def _batch_args(plans, problems, outs):
