@@ -165,6 +165,27 @@ def run_leg(name, steps, warmup, cold, kernel=None, nb=None):
             tg_uv = torch.empty(g_uv.shape, dtype=torch.float32, device=dev)
             tg_w = torch.empty(g_w.shape, dtype=torch.float32, device=dev)
             fn = lambda: plan.table_grad(sub, g_uv, g_w, uvw, vin, out_uv=tg_uv, out_w=tg_w)   # noqa: E731
+    if name == "latency":
+        # 1000 launches captured in one HIP graph, replayed: the per-launch
+        # time of the small plain-line case, as the bench's latency figure
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        fn()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(1000):
+                plan.execute(sub, g_uv, g_w, uvw, out=out, stream=side)
+        torch.cuda.synchronize()
+        for _ in range(warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        ms = [x / 1000.0 for x in launch_times(g.replay, steps)]
+        res = {"leg": name, "workload": p.name, "visibilities": p.n_vis, "graph_launches": 1000,
+               "replays": steps, "per_launch_ms": percentiles(ms), "plan": plan.info(),
+               "source_sha256_16": source_hash(leg["source"])}
+        log(f"leg latency: {res['per_launch_ms']['median'] * 1e3:.2f} us per launch (graph of 1000)")
+        return res
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()

@@ -179,6 +179,8 @@ struct dg_plan_ {
     int32_t cap_adj[kMaxVariants] = {};    // resident workgroups per adjoint variant
     int32_t device = 0;
     int32_t n_cu = 0;
+    int32_t grid_div = 1;                  // persistent grid: resident workgroups / grid_div
+    std::string device_key;                // architecture and CU count, for the tuning cache
     QueueSpec q{};
     DeviceScratch ds;
     hipStream_t last_stream = nullptr;
@@ -324,6 +326,13 @@ dg_status device_capacity(dg_plan_* p) {
     }
     p->device = dev;
     p->n_cu = n_cu;
+    hipDeviceProp_t prop{};
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    std::string arch(prop.gcnArchName);
+    for (char& c : arch)
+        if (c == ':' || c == ' ' || c == '\t') c = '-';
+    p->device_key = arch + "_" + std::to_string(n_cu) + "cu";
     return DG_OK;
 }
 
@@ -332,12 +341,16 @@ std::string tune_key(const dg_plan_* p) {
     int64_t n = p->offsets.back();
     int lg = 0;
     while ((int64_t(1) << (lg + 1)) <= std::max<int64_t>(1, n)) ++lg;
-    k << "grid" << p->desc.grid_dtype << "_gcf" << p->desc.gcf_dtype << "_os" << p->desc.os_uv << "x"
-      << p->desc.os_w << "_S" << p->n_sub << "_log2N" << lg;
+    k << p->device_key << "_grid" << p->desc.grid_dtype << "_gcf" << p->desc.gcf_dtype << "_os" << p->desc.os_uv
+      << "x" << p->desc.os_w << "_nw" << p->desc.n_w << "_S" << p->n_sub << "_log2N" << lg;
     return k.str();
 }
 
-bool tune_cache_lookup(const std::string& key, int32_t* n_b, int32_t* variant) {
+// On-disk tuning cache (DG_TUNE_CACHE): one line per choice, "key n_b
+// variant grid_div"; the key names the device (architecture and CU count)
+// and the problem's shape class, so a choice is reused only on the device
+// type it was timed on. The last line for a key wins.
+bool tune_cache_lookup(const std::string& key, int32_t* n_b, int32_t* variant, int32_t* grid_div) {
     const char* path = std::getenv("DG_TUNE_CACHE");
     if (!path) return false;
     std::ifstream f(path);
@@ -346,22 +359,24 @@ bool tune_cache_lookup(const std::string& key, int32_t* n_b, int32_t* variant) {
     while (std::getline(f, line)) {
         std::istringstream ls(line);
         std::string k;
-        int nb = 0, var = 0;
+        int nb = 0, var = 0, div = 1;
         if (ls >> k >> nb >> var && k == key && nb >= 1 && nb <= kMaxNb && var >= 0 &&
             var < degrid_variant_count()) {
+            if (!(ls >> div) || div < 1 || div > 2) div = 1;
             *n_b = nb;
             *variant = var;
-            found = true;   // the last entry for a key wins
+            *grid_div = div;
+            found = true;
         }
     }
     return found;
 }
 
-void tune_cache_store(const std::string& key, int32_t n_b, int32_t variant) {
+void tune_cache_store(const std::string& key, int32_t n_b, int32_t variant, int32_t grid_div) {
     const char* path = std::getenv("DG_TUNE_CACHE");
     if (!path) return;
     std::ofstream f(path, std::ios::app);
-    f << key << " " << n_b << " " << variant << "\n";
+    f << key << " " << n_b << " " << variant << " " << grid_div << "\n";
 }
 
 // Default tile size and kernel variant when neither the caller nor the tuning
@@ -369,6 +384,21 @@ void tune_cache_store(const std::string& key, int32_t n_b, int32_t variant) {
 // 16-bit storage types gather through the caches (their cells are half as
 // wide, and the staging copy costs more than it saves).
 constexpr int32_t kDefaultNb = 64;
+// Occupancy settings the tuners try: the persistent grid holds every
+// resident workgroup (1) or half of them (2).
+constexpr int32_t kGridDivs[] = {1, 2};
+
+// Tile size when neither the caller nor the tuning cache chooses: 64, unless
+// the plan is so small that tiles of 64 would leave most of the device's
+// resident wavefronts without work (fewer than 16 visibilities per resident
+// wavefront); then smaller tiles (a multiple of 8, at least 8), about four
+// wavefronts' worth of visibilities each, so that more wavefronts share the
+// launch and each one's chain of dependent loads is shorter.
+int32_t default_nb(int64_t n_vis, int64_t resident_waves) {
+    if (resident_waves <= 0 || n_vis >= 16 * resident_waves) return kDefaultNb;
+    const int64_t per = (4 * n_vis + resident_waves - 1) / resident_waves;
+    return (int32_t)std::min<int64_t>(kDefaultNb, std::max<int64_t>(8, (per + 7) / 8 * 8));
+}
 int32_t default_variant(const dg_desc& d) { return d.grid_dtype == DG_GRID_C64 ? 4 : 0; }
 
 // Subgrids with more w planes than the w support have taps that start at any
@@ -406,7 +436,7 @@ dg_status rebuild_tiles(dg_plan_* p, int32_t n_b_req, hipStream_t stream) {
     p->version++;
     p->q = split_queues(tiles);
     p->tiles.swap(tiles);
-    p->blocks = blocks_for(p->cap[p->variant], p->ds.n_tiles);
+    p->blocks = blocks_for(std::max(1, p->cap[p->variant] / p->grid_div), p->ds.n_tiles);
     p->blocks_adj = blocks_for(p->cap_adj[p->variant], p->ds.n_tiles);
     return DG_OK;
 }
@@ -494,11 +524,13 @@ dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_o
     p->desc = *d;
     p->n_sub = n_subgrids;
     p->offsets.assign(vis_offsets, vis_offsets + n_subgrids + 1);
-    int32_t n_b = d->n_b, variant = default_variant(*d);
-    if (n_b == 0 && !tune_cache_lookup(tune_key(p), &n_b, &variant)) n_b = kDefaultNb;
+    int32_t n_b = d->n_b, variant = default_variant(*d), grid_div = 1;
+    s = device_capacity(p);
+    if (s == DG_OK && n_b == 0 && !tune_cache_lookup(tune_key(p), &n_b, &variant, &grid_div))
+        n_b = default_nb(p->offsets.back(), (int64_t)p->cap[variant] * kWavesPerBlock);
+    p->grid_div = grid_div;
     if (!variant_allowed(*d, variant)) variant = kDeepVariant;
     p->variant = variant;
-    s = device_capacity(p);
     if (s == DG_OK) s = rebuild_tiles(p, n_b, stream);
     if (s != DG_OK) {
         free_scratch(p->ds);
@@ -725,8 +757,13 @@ dg_status degrid_tune(dg_plan p, const void* subgrids, const void* g_uv, const v
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
+    // Axes: the gather kernel variant (tap-per-lane mapping with LDS boxes of
+    // several sizes or through the caches, the D1 mapping, the deep-stack
+    // reader), the tile size, and the occupancy of the persistent grid (all
+    // resident workgroups, or half of them). One visibility per tile is left
+    // out: it was 2-12x slower at every count measured.
     float best_ms = 1e30f;
-    int32_t best_nb = p->n_b, best_var = p->variant;
+    int32_t best_nb = p->n_b, best_var = p->variant, best_div = p->grid_div;
     dg_status st = DG_OK;
     for (int var = 0; var < degrid_variant_count() && st == DG_OK; ++var) {
         if (!variant_allowed(p->desc, var)) continue;
@@ -734,28 +771,33 @@ dg_status degrid_tune(dg_plan p, const void* subgrids, const void* g_uv, const v
             p->variant = var;
             st = rebuild_tiles(p, nb, stream);
             if (st != DG_OK) break;
-            const int reps = 5;
-            for (int r = 0; r < 2 && st == DG_OK; ++r)
-                st = degrid_execute(p, subgrids, g_uv, g_w, uvw, vis_out, stream);
-            (void)hipEventRecord(e0, stream);
-            for (int r = 0; r < reps && st == DG_OK; ++r)
-                st = degrid_execute(p, subgrids, g_uv, g_w, uvw, vis_out, stream);
-            (void)hipEventRecord(e1, stream);
-            he = hipEventSynchronize(e1);
-            if (st != DG_OK) break;
-            if (he != hipSuccess) { st = hip_fail(he, "hipEventSynchronize"); break; }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) { best_ms = ms; best_nb = nb; best_var = var; }
+            for (int32_t div : kGridDivs) {
+                p->grid_div = div;
+                p->blocks = blocks_for(std::max(1, p->cap[p->variant] / div), p->ds.n_tiles);
+                const int reps = 5;
+                for (int r = 0; r < 2 && st == DG_OK; ++r)
+                    st = degrid_execute(p, subgrids, g_uv, g_w, uvw, vis_out, stream);
+                (void)hipEventRecord(e0, stream);
+                for (int r = 0; r < reps && st == DG_OK; ++r)
+                    st = degrid_execute(p, subgrids, g_uv, g_w, uvw, vis_out, stream);
+                (void)hipEventRecord(e1, stream);
+                he = hipEventSynchronize(e1);
+                if (st != DG_OK) break;
+                if (he != hipSuccess) { st = hip_fail(he, "hipEventSynchronize"); break; }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) { best_ms = ms; best_nb = nb; best_var = var; best_div = div; }
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != DG_OK) return st;
     p->variant = best_var;
+    p->grid_div = best_div;
     st = rebuild_tiles(p, best_nb, stream);
     if (st != DG_OK) return st;
-    tune_cache_store(tune_key(p), best_nb, best_var);
+    tune_cache_store(tune_key(p), best_nb, best_var, best_div);
     return DG_OK;
 }
 
@@ -885,7 +927,7 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
     s = alloc_scratch(b->ds, tiles, perms, nullptr);
     if (s != DG_OK) return bail(s);
     b->q = split_queues(tiles);
-    b->blocks = blocks_for(plans[0]->cap[b->variant], b->ds.n_tiles);
+    b->blocks = blocks_for(std::max(1, plans[0]->cap[b->variant] / plans[0]->grid_div), b->ds.n_tiles);
     e = hipMalloc(&b->d_probs, sizeof(Problem) * n);
     if (e != hipSuccess) { b->d_probs = nullptr; return bail(hip_fail(e, "hipMalloc(problem table)")); }
     e = hipHostMalloc(&b->h_probs, sizeof(Problem) * n, hipHostMallocDefault);
@@ -999,7 +1041,7 @@ dg_status degrid_batch_tune(const dg_plan* plans, int32_t n, const void* const* 
         return hip_fail(he, "hipEventCreate");
     }
     float best_ms = 1e30f;
-    int32_t best_var = plans[0]->variant, best_nb = plans[0]->n_b;
+    int32_t best_var = plans[0]->variant, best_nb = plans[0]->n_b, best_div = plans[0]->grid_div;
     dg_status st = DG_OK;
     bool any_deep = false;
     for (int32_t i = 0; i < n; ++i) any_deep = any_deep || deep_only(plans[i]->desc);
@@ -1015,27 +1057,32 @@ dg_status degrid_batch_tune(const dg_plan* plans, int32_t n, const void* const* 
                 st = rebuild_tiles(plans[i], nb, stream);
             }
             if (st != DG_OK) break;
-            dg_batch b = nullptr;
-            st = degrid_batch_plan(plans, n, &b);
+            for (int32_t div : kGridDivs) {
+                plans[0]->grid_div = div;   // the batch's grid follows plan 0
+                dg_batch b = nullptr;
+                st = degrid_batch_plan(plans, n, &b);
+                if (st != DG_OK) break;
+                const int reps = 5;
+                for (int r = 0; r < 2 && st == DG_OK; ++r) st = degrid_batch_execute(b, args, stream);
+                (void)hipEventRecord(e0, stream);
+                for (int r = 0; r < reps && st == DG_OK; ++r) st = degrid_batch_execute(b, args, stream);
+                (void)hipEventRecord(e1, stream);
+                he = hipEventSynchronize(e1);
+                (void)degrid_batch_destroy(b);
+                if (st != DG_OK) break;
+                if (he != hipSuccess) { st = hip_fail(he, "hipEventSynchronize"); break; }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) { best_ms = ms; best_var = var; best_nb = nb; best_div = div; }
+            }
             if (st != DG_OK) break;
-            const int reps = 5;
-            for (int r = 0; r < 2 && st == DG_OK; ++r) st = degrid_batch_execute(b, args, stream);
-            (void)hipEventRecord(e0, stream);
-            for (int r = 0; r < reps && st == DG_OK; ++r) st = degrid_batch_execute(b, args, stream);
-            (void)hipEventRecord(e1, stream);
-            he = hipEventSynchronize(e1);
-            (void)degrid_batch_destroy(b);
-            if (st != DG_OK) break;
-            if (he != hipSuccess) { st = hip_fail(he, "hipEventSynchronize"); break; }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) { best_ms = ms; best_var = var; best_nb = nb; }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     for (int32_t i = 0; i < n; ++i) {
         plans[i]->variant = best_var;
+        plans[i]->grid_div = best_div;
         const dg_status s2 = rebuild_tiles(plans[i], best_nb, stream);
         if (st == DG_OK) st = s2;
     }

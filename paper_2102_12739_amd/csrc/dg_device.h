@@ -49,6 +49,10 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Waits until this wavefront's vector-memory operations (loads, stores and
+// atomics) have been performed.
+__device__ __forceinline__ void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // ---------------------------------------------------------------------------
 // Tile queue
 // ---------------------------------------------------------------------------
@@ -98,6 +102,7 @@ struct TileClaims {
     int lim;
     int stride;
     int dbeg;     // first tile of queue q handed out by its cursor
+    int only_static;   // every tile is dealt statically: no cursor, no stealing
 };
 
 // Workgroup b serves queue b mod n_queues: workgroups are placed on the XCDs
@@ -116,6 +121,7 @@ __device__ __forceinline__ TileClaims start_claims(const QueueSpec& qs, const St
         st.stride = uniform(d.stride[st.q]);
     }
     st.dbeg = uniform(d.sbase[st.q]);
+    st.only_static = uniform(d.all_static);
     return st;
 }
 
@@ -134,6 +140,7 @@ __device__ __forceinline__ int claim_tile(const QueueSpec& qs, const StaticDeal&
         st.next += st.stride;
         return t;
     }
+    if (st.only_static) return -1;
     while (st.tried < qs.n_queues) {
         uint32_t idx = 0;
         if (lane_id() == 0) idx = atomicAdd(&ctl->cursor[st.q].v[0], 1u);
@@ -152,7 +159,7 @@ __device__ __forceinline__ int claim_tile(const QueueSpec& qs, const StaticDeal&
 constexpr uint32_t kStaticClaim = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t claim_issue(Ctl* ctl, const TileClaims& st) {
-    if (st.next < st.lim) return kStaticClaim;
+    if (st.next < st.lim || st.only_static) return kStaticClaim;
     uint32_t idx = 0;
     if (lane_id() == 0) idx = atomicAdd(&ctl->cursor[st.q].v[0], 1u);
     return idx;
@@ -170,15 +177,21 @@ __device__ __forceinline__ int claim_resolve(const QueueSpec& qs, const StaticDe
 
 // Adds this wavefront's out-of-range count; the last workgroup of the launch
 // publishes the launch total and resets cursors and counters for the next.
+// The workgroups talk through device-scope atomics only, which are performed
+// beyond the L2 caches: waiting for this workgroup's count to be performed
+// (vmcnt 0) before its increment of the finished-workgroup counter orders
+// the two, and the last workgroup's exchange then reads every count. No L2
+// write-back is needed (the kernel's own end writes the caches back).
 __device__ __forceinline__ void finish_launch(Ctl* ctl, uint32_t wave_oob) {
     auto* oob = reinterpret_cast<unsigned long long*>(&ctl->oob.v[0]);
     if (lane_id() == 0 && wave_oob != 0u) atomicAdd(&oob[0], (unsigned long long)wave_oob);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wait_vmem_all();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
         const uint32_t prev = atomicAdd(&ctl->done.v[0], 1u);
         if (prev == gridDim.x - 1) {
-            __threadfence();
             const unsigned long long total = atomicExch(&oob[0], 0ull);
             atomicExch(&oob[1], total);
             for (int q = 0; q < kMaxQueues; ++q) atomicExch(&ctl->cursor[q].v[0], 0u);

@@ -204,10 +204,15 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
     constexpr int kCellFloats = kSupportW * 2;          // complex64 x 4 w
     constexpr int kRowFloats = B * kCellFloats;         // floats of one block row
     constexpr int kRowVec = kRowFloats / 4;             // float4 per block row
-    // LDS row pitch: 16 bytes more than a row (cells stay 16-byte aligned and
-    // neighbouring rows start on different banks)
-    constexpr int kPitch = kRowFloats + 4;
-    __shared__ __attribute__((aligned(16))) float s_box[kWavesPerBlock][B * kPitch];
+    // LDS copy of the block in two planes of 16-byte slots: plane 0 holds w 0-1
+    // of every cell, plane 1 (kPlane floats further) w 2-3. Cell (cy, cx) sits
+    // in slot cy * B + (cx ^ 8 * (cy & 1)): the eight lanes of a tap row then
+    // touch one 128-byte span (at most two runs) of a plane, and the rows of
+    // odd and even cy that one LDS cycle serves fall on opposite halves of
+    // the banks (no padding needed).
+    constexpr int kPlane = B * B * 4;
+    __shared__ __attribute__((aligned(16))) float s_box[kWavesPerBlock][2 * kPlane];
+    auto slot_of = [](int cy, int cx) { return cy * B + (cx ^ ((cy & 1) << 3)); };
 
     const int lane = lane_id();
     const int wv = (int)(threadIdx.x / kWave);
@@ -237,11 +242,12 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
         float* out = static_cast<float*>(pr.grid_out) +
                      2 * ((int64_t)s * pr.cells_per_sub + ((int64_t)(by * B) * pr.n_u + bx * B) * pr.n_w);
 
-        // the block's current contents (or zeros), 16 bytes per lane and step
+        // the block's current contents (or zeros), 16 bytes per lane and step:
+        // chunk col of a row is half (col & 1) of cell col / 2
 #pragma unroll
         for (int f = lane; f < B * kRowVec; f += kWave) {
             const int row = f / kRowVec, col = f - row * kRowVec;
-            *reinterpret_cast<float4*>(box + row * kPitch + col * 4) =
+            *reinterpret_cast<float4*>(box + (col & 1) * kPlane + slot_of(row, col >> 1) * 4) =
                 P.accumulate ? *reinterpret_cast<const float4*>(out + row * row_floats + col * 4)
                              : make_float4(0.f, 0.f, 0.f, 0.f);
         }
@@ -297,14 +303,15 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
                             // the taps of one visibility are distinct cells and
                             // LDS operations of a wavefront run in order, so a
                             // plain read-modify-write is exact
-                            float4* dst = reinterpret_cast<float4*>(box + cy * kPitch + cx * kCellFloats);
-                            float4 a = dst[0], b = dst[1];
+                            float4* dst0 = reinterpret_cast<float4*>(box + slot_of(cy, cx) * 4);
+                            float4* dst1 = reinterpret_cast<float4*>(box + kPlane + slot_of(cy, cx) * 4);
+                            float4 a = *dst0, b = *dst1;
                             a.x += gc[k] * cj[0]; a.y += gc[k] * cj[1];
                             a.z += gc[k] * cj[2]; a.w += gc[k] * cj[3];
                             b.x += gc[k] * cj[4]; b.y += gc[k] * cj[5];
                             b.z += gc[k] * cj[6]; b.w += gc[k] * cj[7];
-                            dst[0] = a;
-                            dst[1] = b;
+                            *dst0 = a;
+                            *dst1 = b;
                         }
                     }
                 }
@@ -317,7 +324,7 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
         for (int f = lane; f < B * kRowVec; f += kWave) {
             const int row = f / kRowVec, col = f - row * kRowVec;
             *reinterpret_cast<float4*>(out + row * row_floats + col * 4) =
-                *reinterpret_cast<const float4*>(box + row * kPitch + col * 4);
+                *reinterpret_cast<const float4*>(box + (col & 1) * kPlane + slot_of(row, col >> 1) * 4);
         }
         wave_lds_sync();
         t = ahead ? t_next : uniform(claim_tile(P.q, P.deal, P.ctl, st));

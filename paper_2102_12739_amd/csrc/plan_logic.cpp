@@ -125,6 +125,22 @@ QueueSpec split_queues_weighted(const std::vector<int64_t>& weights) {
 StaticDeal deal_static(const QueueSpec& q, int blocks, int waves_per_block) {
     StaticDeal d{};
     const int nq = q.n_queues;
+    // every queue holds at most one tile per serving wavefront: all dealt
+    // statically, no cursor and no stealing
+    bool small = nq > 0;
+    for (int k = 0; k < nq; ++k) {
+        const int nb = blocks > k ? (blocks - k + nq - 1) / nq : 0;
+        small = small && nb > 0 && (int64_t)q.end[k] - q.begin[k] <= (int64_t)nb * waves_per_block;
+    }
+    if (small) {
+        for (int k = 0; k < nq; ++k) {
+            d.sbase[k] = q.end[k];
+            d.stride[k] = ((blocks - k + nq - 1) / nq) * waves_per_block;
+        }
+        d.on = 1;
+        d.all_static = 1;
+        return d;
+    }
     for (int k = 0; k < kMaxQueues; ++k) {
         if (k >= nq) continue;
         const int nb = blocks > k ? (blocks - k + nq - 1) / nq : 0;

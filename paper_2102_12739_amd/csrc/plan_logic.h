@@ -82,11 +82,15 @@ QueueSpec split_queues_weighted(const std::vector<int64_t>& weights);
 // tiles from sbase on go through the queue's cursor. A queue gets a static
 // part (kStaticEighths / 8 of its tiles) only when it holds at least
 // kMinTilesPerWave tiles per serving wavefront; otherwise sbase = begin.
+// When no queue holds more tiles than wavefronts serve it, every tile is
+// dealt statically (sbase = end, all_static = 1): each wavefront takes at
+// most one tile, with no cursor atomic and no stealing.
 constexpr int kStaticEighths = 6;
 constexpr int kMinTilesPerWave = 4;
 
 struct StaticDeal {
     int32_t on;                   // 1 when some queue has a static part
+    int32_t all_static;           // 1 when every tile is dealt statically
     int32_t sbase[kMaxQueues];    // first tile of queue q handed out by its cursor
     int32_t stride[kMaxQueues];   // wavefronts serving queue q
 };

@@ -18,10 +18,11 @@
 //    to the output with one coalesced float atomic, so that the two atomic
 //    units work side by side. Float atomics make the order, and so the last
 //    bits, depend on timing;
-//  * dL/dG_w: each lane's four shares are summed over groups of eight lanes
-//    with three DPP steps, and the eight group sums are added to a private
-//    per-wavefront LDS array [o_w][t_w][8] (eight distinct slots per add);
-//    at the end each row is summed and added to the output.
+//  * dL/dG_w: per w tap, the shares of a group of eight visibilities are
+//    summed over the 64 lanes together (the degrid kernel's eight-way
+//    permlane/DPP reduction), and lane 8m adds visibility m's four sums to
+//    a private per-wavefront LDS array [o_w][t_w][8] (eight distinct slots
+//    per add); at the end each row is summed and added to the output.
 #include "dg_device.h"
 
 namespace dg {
@@ -35,36 +36,42 @@ struct GradFetch {
     float gv[kGroup];
 };
 
+// The loads of visibilities g0 .. g0+7 (all of them, without branches, so
+// that the compiler can count the loads in flight and wait for exactly the
+// ones it needs): a visibility out of range or past the tile has the
+// out-of-range offset (its subgrid loads return zeros) and table block 0.
 template <int G, int F, bool DEEP>
-__device__ __forceinline__ void grad_fetch(GradFetch<G>& f, int g0, int count, int a_off, int tab,
-                                           __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rg, uint32_t lane_a,
-                                           bool want_w) {
+__device__ __forceinline__ void grad_fetch(GradFetch<G>& f, int g0, int a_off, int tab,
+                                           __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rg, uint32_t lane_a) {
     const int lane = lane_id();
 #pragma unroll
     for (int k = 0; k < kGroup; ++k) {
-        if (g0 + k < count) {
-            const uint32_t aj = (uint32_t)__builtin_amdgcn_readlane(a_off, g0 + k);
-            if constexpr (DEEP)
-                load_w4_narrow<G>(ra, lane_a + aj, f.raw[k]);
-            else
-                load_w4<G>(ra, lane_a + aj, f.raw[k]);
-            f.gv[k] = want_w ? load_gcf_rsrc<F>(rg, (uint32_t)(__builtin_amdgcn_readlane(tab, g0 + k) + lane) *
-                                                        GcfTraits<F>::kBytes)
-                             : 0.0f;
-        }
+        const uint32_t aj = (uint32_t)__builtin_amdgcn_readlane(a_off, g0 + k);
+        if constexpr (DEEP)
+            load_w4_narrow<G>(ra, lane_a + aj, f.raw[k]);
+        else
+            load_w4<G>(ra, lane_a + aj, f.raw[k]);
+        f.gv[k] = load_gcf_rsrc<F>(rg, (uint32_t)(__builtin_amdgcn_readlane(tab, g0 + k) + lane) * GcfTraits<F>::kBytes);
     }
 }
 
-constexpr int kWGroups = 8;   // lane groups whose dL/dG_w sums reach LDS
+constexpr int kWGroups = 8;   // per-visibility slots of the dL/dG_w sums in LDS
 
-// Sum of x over the aligned group of eight lanes holding this lane (every
-// lane of the group gets it): quad exchanges, then the mirror inside each
-// half row pairs quad 0 with quad 1.
-__device__ __forceinline__ float sum8_lanes(float x) {
-    x += dpp<kDppQuadXor1>(x);
-    x += dpp<kDppQuadXor2>(x);
-    x += dpp<kDppRowHalfMirror>(x);
-    return x;
+// w value tw of one fetched cell, widened to float32.
+template <int G>
+__device__ __forceinline__ void widen_one(const uint32_t (&raw)[GridTraits<G>::kWords], int tw, float& re,
+                                          float& im) {
+    if constexpr (G == kGridC64) {
+        re = __uint_as_float(raw[2 * tw]);
+        im = __uint_as_float(raw[2 * tw + 1]);
+    } else if constexpr (G == kGridCBF16) {
+        re = __uint_as_float(raw[tw] << 16);
+        im = __uint_as_float(raw[tw] & 0xFFFF0000u);
+    } else {
+        const __half2 h = __builtin_bit_cast(__half2, raw[tw]);
+        re = __low2float(h);
+        im = __high2float(h);
+    }
 }
 
 // LDS_UV: the workgroup accumulates dL/dG_uv in LDS (the table fits).
@@ -120,48 +127,86 @@ __global__ __launch_bounds__(kBlockThreads) void table_grad_kernel(TableGradPara
         // groups of eight in a two-stage pipeline, unrolled over the largest
         // tile so that both buffers stay in registers
         GradFetch<G> buf[2];
-        grad_fetch<G, F, DEEP>(buf[0], 0, count, a_off, tab, ra, rg, lane_a, want_w);
+        grad_fetch<G, F, DEEP>(buf[0], 0, a_off, tab, ra, rg, lane_a);
 #pragma unroll
         for (int g0 = 0; g0 < kMaxNb; g0 += kGroup) {
             if (g0 < count) {
                 const int cur = (g0 / kGroup) & 1;
                 if (g0 + kGroup < kMaxNb && g0 + kGroup < count)
-                    grad_fetch<G, F, DEEP>(buf[cur ^ 1], g0 + kGroup, count, a_off, tab, ra, rg, lane_a, want_w);
+                    grad_fetch<G, F, DEEP>(buf[cur ^ 1], g0 + kGroup, a_off, tab, ra, rg, lane_a);
+                // dL/dV of the group's visibilities (zero for the ones out
+                // of range or past the tile)
+                // (g is 0 on lanes out of range or past the tile, and their
+                // subgrid loads returned zeros: their shares below are 0
+                // without any branch)
+                float gre[kGroup], gim[kGroup];
 #pragma unroll
                 for (int k = 0; k < kGroup; ++k) {
-                    const int j = g0 + k;
-                    if (j >= count || !((live >> j) & 1ull)) continue;   // wave-uniform
-                    float re[4], im[4];
-                    widen_w4<G>(buf[cur].raw[k], re, im);
-                    const float gre = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g.x), j));
-                    const float gim = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g.y), j));
-                    if (want_uv) {
-                        const float4 gw = load_gw_row<F>(g_w, (uint32_t)__builtin_amdgcn_readlane((int)gw_off, j));
+                    gre[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g.x), g0 + k));
+                    gim[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g.y), g0 + k));
+                }
+                if (want_uv) {
+                    // the eight G_w rows' scalar loads go out together, then
+                    // the eight shares, then the atomics back to back (an
+                    // LDS atomic between two scalar loads would make the
+                    // second one's wait also wait for the atomic)
+                    float4 gwr[kGroup];
+#pragma unroll
+                    for (int k = 0; k < kGroup; ++k)
+                        gwr[k] = load_gw_row<F>(g_w, (uint32_t)__builtin_amdgcn_readlane((int)gw_off, g0 + k));
+                    float val[kGroup];
+#pragma unroll
+                    for (int k = 0; k < kGroup; ++k) {
+                        float re[4], im[4];
+                        widen_w4<G>(buf[cur].raw[k], re, im);
+                        const float4 gw = gwr[k];
                         const float sr = gw.x * re[0] + gw.y * re[1] + gw.z * re[2] + gw.w * re[3];
                         const float si = gw.x * im[0] + gw.y * im[1] + gw.z * im[2] + gw.w * im[3];
+                        val[k] = gre[k] * sr + gim[k] * si;
+                    }
+#pragma unroll
+                    for (int k = 0; k < kGroup; ++k) {
+                        const int j = g0 + k;
+                        if (!((live >> j) & 1ull)) continue;   // wave-uniform: no atomic for nothing
                         const int e = __builtin_amdgcn_readlane(tab, j) + lane;
                         // LDS float atomics and global float atomics run in
-                        // different units at similar rates (about 120 cycles
-                        // per 64-lane add to LDS per CU): alternate visibilities
-                        // go to each, so that the two overlap
+                        // different units: alternate visibilities go to each,
+                        // so that the two overlap
                         if (LDS_UV && (k & 1) == 0)
-                            atomicAdd(s_uv + e, gre * sr + gim * si);
+                            atomicAdd(s_uv + e, val[k]);
                         else
-                            atomicAdd(P.grad_uv + e, gre * sr + gim * si);
+                            atomicAdd(P.grad_uv + e, val[k]);
                     }
-                    if (want_w) {
-                        const int row = __builtin_amdgcn_readlane(ow, j) * kSupportW;
-                        const float gv = buf[cur].gv[k];
-                        float r[kSupportW];
+                }
+                if (want_w) {
+                    // per w tap: the eight visibilities' shares summed over
+                    // the 64 lanes together (reduce8: lane l ends with
+                    // visibility l / 8's sum), then one add per visibility
+                    // by lane 8m into this wavefront's own slots (LDS
+                    // operations of a wavefront run in order)
+                    float r[kSupportW];
 #pragma unroll
-                        for (int tw = 0; tw < kSupportW; ++tw) r[tw] = sum8_lanes(gv * (gre * re[tw] + gim * im[tw]));
-                        // lane 8m holds group m's sums; the slots are this
-                        // wavefront's own, and LDS operations of a wavefront
-                        // run in order
-                        if ((lane & (kWGroups - 1)) == 0) {
+                    for (int tw = 0; tw < kSupportW; ++tw) {
+                        float x[kGroup];
 #pragma unroll
-                            for (int tw = 0; tw < kSupportW; ++tw) acc[(row + tw) * kWGroups + (lane >> 3)] += r[tw];
+                        for (int k = 0; k < kGroup; ++k) {
+                            float re1, im1;
+                            widen_one<G>(buf[cur].raw[k], tw, re1, im1);
+                            x[k] = buf[cur].gv[k] * (gre[k] * re1 + gim[k] * im1);
                         }
+                        reduce8(x);
+                        r[tw] = x[0];
+                    }
+                    int row = 0;   // G_w row of visibility g0 + lane / 8
+#pragma unroll
+                    for (int k = 0; k < kGroup; ++k) {
+                        const int o = __builtin_amdgcn_readlane(ow, g0 + k);
+                        row = (lane >> 3) == k ? o : row;
+                    }
+                    if ((lane & (kWGroups - 1)) == 0) {
+#pragma unroll
+                        for (int tw = 0; tw < kSupportW; ++tw)
+                            acc[(row * kSupportW + tw) * kWGroups + (lane >> 3)] += r[tw];
                     }
                 }
             }

@@ -41,7 +41,8 @@ int main(int argc, char** argv) {
         const auto tiles = dg::build_tiles((int64_t)off.size() - 1, off.data(), nb, 0);
         const dg::QueueSpec q = dg::split_queues(tiles);
         const dg::StaticDeal d = dg::deal_static(q, blocks, 4);
-        std::printf("{\"n_queues\": %d, \"on\": %d, \"begin\": [", q.n_queues, d.on);
+        std::printf("{\"n_queues\": %d, \"on\": %d, \"all_static\": %d, \"begin\": [", q.n_queues, d.on,
+                    d.all_static);
         for (int i = 0; i < q.n_queues; ++i) std::printf("%s%d", i ? ", " : "", q.begin[i]);
         std::printf("], \"end\": [");
         for (int i = 0; i < q.n_queues; ++i) std::printf("%s%d", i ? ", " : "", q.end[i]);

@@ -217,14 +217,16 @@ def test_queues_partition_the_tile_list_and_balance_visibilities(plan_logic, nb,
 @pytest.mark.parametrize("nb,blocks,counts", [
     (64, 512, list(np.random.default_rng(3).integers(2 ** 10, 2 ** 18, 64))),   # paper-scale shape
     (64, 768, [65536] * 16), (64, 8, [1024, 1024]), (16, 3, [5000, 7000]), (8, 20, [3, 3, 3]),
-    (32, 1, [100000]), (64, 512, [10]),
+    (32, 1, [100000]), (64, 512, [10]), (8, 64, [1024, 1024]), (8, 7, [100, 90]), (8, 8, [129, 128]),
 ])
 def test_static_deal_gives_every_tile_to_exactly_one_claim(plan_logic_exe, nb, blocks, counts):
     """The launch's static deal (workgroup b serves queue b mod n_queues;
     wavefront r of a queue's workgroups takes begin + r, begin + r + stride,
     ... below sbase) together with the queue cursors (tiles sbase .. end)
     hands out every tile exactly once; a queue gets a static part only with
-    at least 4 tiles per serving wavefront, and then 6/8 of its tiles."""
+    at least 4 tiles per serving wavefront, and then 6/8 of its tiles;
+    when no queue holds more tiles than serving wavefronts, every tile is
+    dealt statically (all_static, one tile per wavefront at most)."""
     r = subprocess.run([plan_logic_exe, "deal", str(nb), str(blocks), *map(str, counts)], capture_output=True, text=True,
                        check=True)
     d = json.loads(r.stdout)
@@ -232,13 +234,18 @@ def test_static_deal_gives_every_tile_to_exactly_one_claim(plan_logic_exe, nb, b
     n_tiles = d["end"][-1] if nq else 0
     seen = np.zeros(n_tiles, dtype=np.int64)
     any_static = False
+    small = nq > 0 and all(len(range(q, blocks, nq)) > 0 and d["end"][q] - d["begin"][q] <= 4 * len(range(q, blocks, nq))
+                           for q in range(nq))
+    assert d["all_static"] == int(small)
     for q in range(nq):
         b, e, sb, w = d["begin"][q], d["end"][q], d["sbase"][q], d["stride"][q]
         nb_q = len(range(q, blocks, nq))
         assert w == 4 * nb_q
         assert b <= sb <= e
         size = e - b
-        if nb_q > 0 and size >= 4 * w:
+        if small:
+            assert sb == e and size <= w
+        elif nb_q > 0 and size >= 4 * w:
             assert sb - b == size * 6 // 8
         else:
             assert sb == b
