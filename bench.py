@@ -612,12 +612,18 @@ def main(argv=None):
     ap.add_argument("--cold", action="store_true", help="with --leg: flush 1 GiB before every timed launch")
     ap.add_argument("--kernel", type=int, default=None, help="with --leg: the gather kernel variant")
     ap.add_argument("--nb", type=int, default=None, help="with --leg and --kernel: visibilities per tile")
+    ap.add_argument("--study-md", metavar="JSON",
+                    help="instead of the benchmark: render the JSON line of a --study run as markdown tables")
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="instead of the benchmark: read rocprofv3 counter runs of the legs under DIR "
                          "(one folder per run, named LEG__PASS) and write profiles/counters.json and .md")
     args = ap.parse_args(argv)
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc)
+        return 0
+    if args.study_md:
+        with open(args.study_md) as f:
+            print(study_markdown(json.loads(f.read().strip().splitlines()[-1])))
         return 0
     if args.leg:
         print(json.dumps(run_leg(args.leg, args.steps, args.warmup, args.cold, args.kernel, args.nb)), flush=True)
@@ -1118,6 +1124,47 @@ def bench_latency(launches=1000, replays=5):
            "label": "latency (launch-bound: the work is a few microseconds)"}
     log(f"latency: graph {res['graph_us_per_launch']['median']:.2f} us/launch, eager {eager_us:.2f} us/launch")
     return res
+
+
+def study_markdown(study):
+    """Markdown tables of a --study result: per scenario and count, the best
+    vis/s of each mapping over the two work orders ("s": the sorted order)."""
+    rows = study["rows"]
+    maps = []
+    for r in rows:
+        if r["mapping"] not in maps:
+            maps.append(r["mapping"])
+    best = {}
+    for r in rows:
+        k = (r["scenario"], r["n_per_subgrid_max"], r["mapping"])
+        if k not in best or r["vis_per_s"] > best[k]["vis_per_s"]:
+            best[k] = r
+    out = [f"# {study['study']}: {study['subgrids']} subgrids of 512 x 512 x 4, line-shaped visibilities", "",
+           "Command: `python3 bench.py --study --steps 10 --warmup 3 > study.json`, then "
+           "`python3 bench.py --study-md study.json`. Median kernel time of the timed launches; vis/s per mapping, "
+           "the better of input order and the plan-time work order (\"s\": sorted). \"equal\": every subgrid N "
+           "visibilities; \"ramp\": subgrid k of 16 has N (k + 1) / 16.", ""]
+    for sc in ("equal", "ramp"):
+        ns = sorted({r["n_per_subgrid_max"] for r in rows if r["scenario"] == sc})
+        out += [f"## {sc}", "", "| N | " + " | ".join(maps) + " | best | D1-like / best |",
+                "|---|" + "---|" * (len(maps) + 2)]
+        for n in ns:
+            cells, top, top_m, d1 = [], 0.0, "", 0.0
+            for m in maps:
+                r = best.get((sc, n, m))
+                if r is None:
+                    cells.append("-")
+                    continue
+                v = r["vis_per_s"]
+                cells.append(f"{v:.3g}" + (" s" if r["order"] == "sorted" else ""))
+                if v > top:
+                    top, top_m = v, m
+                if m.startswith("D1"):
+                    d1 = max(d1, v)
+            exp = n.bit_length() - 1
+            out.append(f"| 2^{exp} | " + " | ".join(cells) + f" | {top_m} | {d1 / top:.2f} |")
+        out.append("")
+    return "\n".join(out)
 
 
 def bench_study(steps, warmup):
