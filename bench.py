@@ -669,12 +669,19 @@ def main(argv=None):
         tune_s = time.perf_counter() - t
     info = plan.info()
     run = lambda: plan.execute(*inputs, out=out)   # noqa: E731
-    # warm: back-to-back launches (wall time and HIP events over the region)
-    ms_warm_step, ms_warm_kernel = time_plan(plan, inputs, out, args.steps, args.warmup)
-    # cold (the headline): each timed launch follows an untimed 1 GiB write
-    # that flushes the L2 and the Infinity Cache
+    # warm: back-to-back launches (wall time and HIP events over the region);
+    # left out with --main-only, so that a profiler's per-kernel average
+    # covers the cold launches only
+    ms_warm_step = ms_warm_kernel = None
+    if not args.main_only:
+        ms_warm_step, ms_warm_kernel = time_plan(plan, inputs, out, args.steps, args.warmup)
+    # cold (the headline): each launch follows an untimed 1 GiB write that
+    # flushes the L2 and the Infinity Cache; warmup launches too
     flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda:0")
     flush = lambda: flush_buf.fill_(1.0)   # noqa: E731
+    for _ in range(args.warmup):
+        flush()
+        run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cold_ms = launch_times(run, args.steps, flush=flush)
@@ -685,7 +692,7 @@ def main(argv=None):
     comp = compulsory_bytes(p, 8)
     counters = committed_counters("degrid")
     roof = roofline_object(p.n_vis, BYTES_PER_VIS["c64"], ms_step, comp, counters, "degrid_kernel<c64,f32>")
-    log(f"fp32: cold {ms_step:.4f} ms/launch ({value:.4g} vis/s), warm {ms_warm_step:.4f} ms/step; "
+    log(f"fp32: cold {ms_step:.4f} ms/launch ({value:.4g} vis/s), warm {ms_warm_step} ms/step; "
         f"bound {roof['bound']} at {roof['frac']:.2%}")
 
     result = {
@@ -711,7 +718,7 @@ def main(argv=None):
         "roofline": roof,
         "timing": {"cold_kernel_ms": percentiles(cold_ms), "cold_region_wall_s": cold_wall_s,
                    "warm_ms_per_step": ms_warm_step, "warm_kernel_ms_mean": ms_warm_kernel,
-                   "warm_value": p.n_vis / (ms_warm_step * 1e-3)},
+                   "warm_value": p.n_vis / (ms_warm_step * 1e-3) if ms_warm_step else None},
     }
     # Per-launch distribution back to back, the memory system's plain-copy rate
     if not args.main_only:
