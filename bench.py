@@ -418,21 +418,21 @@ def roofline_object(n_vis, bytes_per_vis, kernel_ms, comp_bytes, counters, kerne
             hbm["frac"] = hbm["achieved_gbs"] / HBM_PEAK_GBS
             hbm["bytes_per_vis"] = traffic / n_vis
             fracs["hbm"] = hbm["frac"]
-        if kc.get("SQ_INSTS_LDS") is not None:
-            # every LDS instruction of this kernel moves at most 16 bytes per lane
-            lds_bytes = kc["SQ_INSTS_LDS"] * 64 * 16
-            res["lds"] = {"instructions": kc["SQ_INSTS_LDS"], "bytes_upper": lds_bytes,
+        if kc.get("SQ_INSTS_LDS_LOAD_BANDWIDTH") is not None:
+            lds_bytes = 64.0 * (kc["SQ_INSTS_LDS_LOAD_BANDWIDTH"] + kc.get("SQ_INSTS_LDS_STORE_BANDWIDTH", 0.0))
+            res["lds"] = {"bytes": lds_bytes, "instructions": kc.get("SQ_INSTS_LDS"),
                           "achieved_gbs": lds_bytes / t / 1e9, "peak_gbs": LDS_PEAK_GBS,
-                          "frac": lds_bytes / t / 1e9 / LDS_PEAK_GBS,
-                          "basis": "SQ_INSTS_LDS x 64 lanes x 16 B (the widest LDS access of the kernel)"}
+                          "frac": lds_bytes / t / 1e9 / LDS_PEAK_GBS, "busy_pct": kc.get("LdsUtil"),
+                          "basis": "64 B x (SQ_INSTS_LDS_LOAD_BANDWIDTH + SQ_INSTS_LDS_STORE_BANDWIDTH)"}
             fracs["lds"] = res["lds"]["frac"]
         if kc.get("SQ_INSTS_VALU") is not None:
             gi = kc["SQ_INSTS_VALU"] / t / 1e9
-            res["valu"] = {"instructions": kc["SQ_INSTS_VALU"], "achieved_ginst_s": gi,
-                           "peak_ginst_s": VALU_PEAK_GINST, "frac": gi / VALU_PEAK_GINST,
-                           "basis": "wave64 VALU instructions, 4 clocks each on a 16-lane SIMD"}
-            fracs["valu"] = res["valu"]["frac"]
-        for k in ("SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "TCC_HIT_sum", "TCC_MISS_sum"):
+            res["alu"] = {"instructions": kc["SQ_INSTS_VALU"], "achieved_ginst_s": gi,
+                          "peak_ginst_s": VALU_PEAK_GINST, "frac": gi / VALU_PEAK_GINST,
+                          "basis": "wave64 vector-ALU instructions (SQ_INSTS_VALU) issued, one per 4 clocks "
+                                   "per SIMD (16 lanes, no packed FP32): 256 CUs x 4 SIMDs x 2.4 GHz / 4"}
+            fracs["alu"] = res["alu"]["frac"]
+        for k in ("VALUBusy", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "TCC_HIT_sum", "TCC_MISS_sum"):
             if kc.get(k) is not None:
                 res.setdefault("counters", {})[k] = kc[k]
         if kc.get("TCC_HIT_sum") and kc.get("TCC_MISS_sum"):
@@ -445,11 +445,11 @@ def roofline_object(n_vis, bytes_per_vis, kernel_ms, comp_bytes, counters, kerne
     bound = max(fracs, key=fracs.get)
     top = {"hbm": (hbm["achieved_gbs"], HBM_PEAK_GBS, "GB/s"),
            "lds": (res.get("lds", {}).get("achieved_gbs"), LDS_PEAK_GBS, "GB/s"),
-           "valu": (res.get("valu", {}).get("achieved_ginst_s"), VALU_PEAK_GINST, "Ginst/s")}[bound]
+           "alu": (res.get("alu", {}).get("achieved_ginst_s"), VALU_PEAK_GINST, "Ginst/s")}[bound]
     res.update({"bound": bound, "achieved": top[0], "peak": top[1], "unit": top[2], "frac": fracs[bound],
                 "traffic": traffic, "fracs": fracs})
     return {k: res[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "fracs", "kernel",
-                                "kernel_ms", "hbm") + tuple(k for k in ("lds", "valu", "counters") if k in res)
+                                "kernel_ms", "hbm") + tuple(k for k in ("lds", "alu", "counters") if k in res)
             + ("effective",)}
 
 
