@@ -321,7 +321,35 @@ PMC_PASSES = (
      "SQ_INSTS_SALU", "SQ_INSTS_SMEM", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR"),
     ("VALUBusy", "LdsUtil", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_ANY",
      "SQ_BUSY_CYCLES"),
+    ("TA_BUSY_avr", "TD_TD_BUSY_sum", "TD_TC_STALL_sum", "GRBM_GUI_ACTIVE", "SQ_WAIT_ANY"),
+    ("TCP_PENDING_STALL_CYCLES_sum", "TCP_TCC_READ_REQ_LATENCY_sum", "TCP_TCC_READ_REQ_sum", "GRBM_GUI_ACTIVE"),
 )
+N_CU = 256   # compute units of the MI355X
+N_XCD = 8    # accelerator complex dies; GRBM_GUI_ACTIVE counts once per die
+
+
+def memory_path(c, n_vis):
+    """Vector-memory path figures of one kernel from its counters, or None:
+    per-CU busy and stall shares of the texture data unit (TD) and the vector
+    L1 (TCP), the L1-to-L2 read latency, L2 reads per visibility and in
+    flight per CU, and the share of wave cycles spent in s_waitcnt."""
+    need = ("GRBM_GUI_ACTIVE", "TD_TD_BUSY_sum", "TCP_TCC_READ_REQ_sum")
+    if any(c.get(k) is None for k in need) or not c["GRBM_GUI_ACTIVE"]:
+        return None
+    cu_cycles = N_CU * c["GRBM_GUI_ACTIVE"] / N_XCD
+    pct = lambda k: 100.0 * c[k] / cu_cycles if c.get(k) is not None else None   # noqa: E731
+    req = c["TCP_TCC_READ_REQ_sum"]
+    lat = c.get("TCP_TCC_READ_REQ_LATENCY_sum")
+    return {"cycles": c["GRBM_GUI_ACTIVE"] / N_XCD,
+            "td_busy_pct": pct("TD_TD_BUSY_sum"), "td_wait_cache_pct": pct("TD_TC_STALL_sum"),
+            "ta_busy_avr_pct": 100.0 * c["TA_BUSY_avr"] * N_XCD / c["GRBM_GUI_ACTIVE"]
+            if c.get("TA_BUSY_avr") is not None else None,
+            "tcp_pending_stall_pct": pct("TCP_PENDING_STALL_CYCLES_sum"),
+            "l2_read_latency_cycles": lat / req if lat is not None and req else None,
+            "l2_reads_per_vis": req / n_vis if n_vis else None,
+            "l2_reads_in_flight_per_cu": lat / cu_cycles if lat is not None else None,
+            "waves_in_waitcnt_pct": 100.0 * c["SQ_WAIT_ANY"] / c["SQ_WAVE_CYCLES"]
+            if c.get("SQ_WAIT_ANY") is not None and c.get("SQ_WAVE_CYCLES") else None}
 
 
 def counters_markdown(out):
@@ -385,6 +413,28 @@ def counters_markdown(out):
                 f"{f(valu, '{:.1f}')} ({f(valu / VALU_PEAK_GINST if valu is not None else None, '{:.3f}')}) | "
                 f"{f(c.get('VALUBusy'), '{:.1f}')} | {f(c.get('LdsUtil'), '{:.1f}')} | "
                 f"{f(c.get('SQ_LDS_BANK_CONFLICT'), '{:.3g}')} | {f(wait, '{:.1f}')} |")
+    lines += [
+        "",
+        "Vector-memory path (TA: texture addresser, TD: texture data unit, TCP: vector L1). Per-CU shares of",
+        f"the kernel's cycles, with cycles = GRBM_GUI_ACTIVE / {N_XCD} (one count per die) over {N_CU} CUs;",
+        "L2 read latency = TCP_TCC_READ_REQ_LATENCY_sum / TCP_TCC_READ_REQ_sum; reads in flight per CU =",
+        "TCP_TCC_READ_REQ_LATENCY_sum / (CUs x cycles); waves in s_waitcnt = SQ_WAIT_ANY / SQ_WAVE_CYCLES.",
+        "",
+        "| leg | kernel | TA busy % | TD busy % | TD waiting on L1 % | L1 stalled on misses % | "
+        "L2 read latency (cycles) | L2 reads / vis | L2 reads in flight / CU | waves in s_waitcnt % |",
+        "|---|---|---|---|---|---|---|---|---|---|",
+    ]
+    for leg, le in sorted(out["legs"].items()):
+        for k, ke in sorted(le["kernels"].items()):
+            m = memory_path(ke["counters"], le.get("visibilities") or 0)
+            if m is None:
+                continue
+            f = lambda x, fmt: (fmt.format(x) if x is not None else "-")   # noqa: E731
+            lines.append(
+                f"| {leg} | {k} | {f(m['ta_busy_avr_pct'], '{:.0f}')} | {f(m['td_busy_pct'], '{:.0f}')} | "
+                f"{f(m['td_wait_cache_pct'], '{:.0f}')} | {f(m['tcp_pending_stall_pct'], '{:.0f}')} | "
+                f"{f(m['l2_read_latency_cycles'], '{:.0f}')} | {f(m['l2_reads_per_vis'], '{:.2f}')} | "
+                f"{f(m['l2_reads_in_flight_per_cu'], '{:.1f}')} | {f(m['waves_in_waitcnt_pct'], '{:.0f}')} |")
     lines += ["", "Compulsory bytes per leg (host count): " + ", ".join(
         f"{leg} {le['compulsory_bytes'] / 1e6:.1f} MB for {le['visibilities']} visibilities"
         for leg, le in sorted(out["legs"].items())), ""]
@@ -437,6 +487,11 @@ def roofline_object(n_vis, bytes_per_vis, kernel_ms, comp_bytes, counters, kerne
                 res.setdefault("counters", {})[k] = kc[k]
         if kc.get("TCC_HIT_sum") and kc.get("TCC_MISS_sum"):
             hbm["l2_hit_rate"] = kc["TCC_HIT_sum"] / (kc["TCC_HIT_sum"] + kc["TCC_MISS_sum"])
+        mp = memory_path(kc, n_vis)
+        if mp is not None:
+            mp["note"] = ("busy and stall shares of the vector-memory path per CU; this, not HBM, LDS or "
+                          "VALU issue, is the resource the kernel keeps occupied")
+            res["memory_path"] = mp
     if not fracs:
         # no counters for this kernel source: the compulsory bytes alone
         fracs["hbm"] = hbm["compulsory_frac"]
@@ -449,7 +504,8 @@ def roofline_object(n_vis, bytes_per_vis, kernel_ms, comp_bytes, counters, kerne
     res.update({"bound": bound, "achieved": top[0], "peak": top[1], "unit": top[2], "frac": fracs[bound],
                 "traffic": traffic, "fracs": fracs})
     return {k: res[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "fracs", "kernel",
-                                "kernel_ms", "hbm") + tuple(k for k in ("lds", "alu", "counters") if k in res)
+                                "kernel_ms", "hbm") + tuple(k for k in ("lds", "alu", "memory_path", "counters")
+                                                            if k in res)
             + ("effective",)}
 
 
