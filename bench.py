@@ -419,6 +419,9 @@ def counters_markdown(out):
         f"the kernel's cycles, with cycles = GRBM_GUI_ACTIVE / {N_XCD} (one count per die) over {N_CU} CUs;",
         "L2 read latency = TCP_TCC_READ_REQ_LATENCY_sum / TCP_TCC_READ_REQ_sum; reads in flight per CU =",
         "TCP_TCC_READ_REQ_LATENCY_sum / (CUs x cycles); waves in s_waitcnt = SQ_WAIT_ANY / SQ_WAVE_CYCLES.",
+        "For kernels of 100 us or more the cycles match the traced duration at 2.26-2.43 GHz; for kernels of",
+        "a few tens of microseconds GRBM_GUI_ACTIVE also counts the profiler's per-dispatch overhead, so their",
+        "shares read low.",
         "",
         "| leg | kernel | TA busy % | TD busy % | TD waiting on L1 % | L1 stalled on misses % | "
         "L2 read latency (cycles) | L2 reads / vis | L2 reads in flight / CU | waves in s_waitcnt % |",
