@@ -62,8 +62,10 @@ def log(*a):
 
 
 _CSRC = os.path.join(ROOT, "paper_2102_12739_amd", "csrc")
-_COMMON_DEVICE = ("dg_device.h", "dg_internal.h", "plan_logic.h")
-# Source files of each profiled kernel (with the device code they include).
+# Source files of each profiled kernel: the device code it includes, and
+# the plan code that decides the work order and cuts the tiles (the counters
+# of a launch depend on both).
+_COMMON_DEVICE = ("dg_device.h", "dg_internal.h", "plan_logic.h", "plan_logic.cpp", "plan_sort.hip")
 LEG_SOURCES = {
     "degrid": ("degrid_kernels.hip",) + _COMMON_DEVICE,
     "adjoint": ("grid_kernels.hip",) + _COMMON_DEVICE,
@@ -794,7 +796,7 @@ def main(argv=None):
     if tune_s is not None:
         result["config"]["tune_s"] = tune_s
     result["config"]["work_order"] = ("input order" if args.input_order else
-                                      "plan-time Z-order of cells (degrid_plan_sort, once per coordinate set)")
+                                      "plan-time Hilbert order of cells (degrid_plan_sort, once per coordinate set)")
     if sort_s is not None:
         result["config"]["plan_sort_s"] = sort_s
     if sort_s is not None and not args.main_only:

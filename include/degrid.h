@@ -255,9 +255,9 @@ dg_status degrid_oob_count(dg_plan p, int64_t* count);
 
 /*
  * Reorder the plan's work for locality: within each subgrid, visibilities are
- * processed in the Z-order (Morton order) of the cell that holds (u, v), so a
- * tile holds visibilities that are close in the subgrid and consecutive tiles
- * cover neighbouring regions (Section 2 notes that one grid point may serve
+ * processed in the order of a Hilbert curve through the cells that hold
+ * (u, v), so a tile holds visibilities that are close in the subgrid and
+ * consecutive tiles cover neighbouring regions (Section 2 notes that one grid point may serve
  * several visibilities; this makes that reuse happen in cache).
  *   uvw  device float64 [N][3], the coordinates later calls will use; NULL
  *        drops the work order (back to input order).

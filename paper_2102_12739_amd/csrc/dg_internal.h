@@ -142,8 +142,8 @@ hipError_t launch_expand_tiles(const Tile* tiles, int64_t n_tiles, const uint32_
 // (through pr.perm), or kNoStart when out of range.
 hipError_t launch_start_cells(const Problem& pr, int64_t n, uint32_t* start, hipStream_t stream);
 
-// Stable sort of each subgrid's visibilities by the Morton code of the cell
-// holding (u, v) (defined in plan_sort.hip). Writes perm[n_vis]: the
+// Stable sort of each subgrid's visibilities by the Hilbert-curve position of
+// the cell holding (u, v) (defined in plan_sort.hip). Writes perm[n_vis]: the
 // visibility index at each position of the new work order. Allocates and
 // frees its own temporary buffers; synchronises 'stream'.
 hipError_t sort_visibilities(const double* uvw, const int64_t* offsets_host, int64_t n_sub,

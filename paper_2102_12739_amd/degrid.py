@@ -266,7 +266,7 @@ class Plan:
         return self.info()
 
     def sort(self, uvw=None, stream=None):
-        """Order the work by subgrid position (Z-order of the cell holding (u, v)).
+        """Order the work by subgrid position (Hilbert order of the cell holding (u, v)).
 
         Outputs stay in input order and unchanged; later calls are faster when
         they use these same coordinates. ``uvw=None`` restores input order.

@@ -202,7 +202,7 @@ def test_injected_allocation_failure(monkeypatch):
 
 
 def test_sorted_work_order_gives_identical_outputs_at_full_size():
-    """degrid_plan_sort reorders the work (Z-order of cells); every visibility
+    """degrid_plan_sort reorders the work (Hilbert order of cells); every visibility
     keeps its own sum, so outputs are bitwise those of the input order."""
     p = wl.paper_scale(seed=1)
     announce("sorted work order, paper scale")
