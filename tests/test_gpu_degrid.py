@@ -352,3 +352,41 @@ def test_largest_supported_subgrid():
     assert rel_l2(g.cpu().numpy(), ref_g) <= REL_L2_FP32
     del t, g
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n_v,n_u", [(16, 65536), (65536, 16)])
+def test_widest_and_tallest_subgrids_at_the_start_cell_limit(n_v, n_u):
+    """Subgrids as wide (or as tall) as the 16-bit first-tap packing allows,
+    with points at the far corners of the valid box: degridding in input
+    order and in the Hilbert work order (whose keys then reach the top of
+    their 16-bit coordinate range) against the oracle, and the adjoint on
+    the sorted plan (owner-computes: both sides are multiples of the 16-cell
+    block, so the block lists reach block index 4095) against the oracle and
+    bitwise repeatable."""
+    p = wl.make_problem("edge", [5000, 3000], seed=31, kind="mixed", n_v=n_v, n_u=n_u)
+    box = wl.interior_box(n_v, n_u, 4)
+    eps = 1e-9
+    corners = [(box.hi[0] - eps, box.hi[1] - eps, box.lo[2]), (box.lo[0], box.hi[1] - eps, box.hi[2] - eps),
+               (box.hi[0] - eps, box.lo[1], box.lo[2]), (box.hi[0] - 0.5, box.hi[1] - 0.5, box.hi[2] - eps)]
+    p.uvw[:len(corners)] = np.array(corners)
+    p.uvw[5000:5000 + len(corners)] = np.array(corners)
+    announce(f"edge subgrids {n_v}x{n_u}x4, N={p.n_vis}")
+    t = upload(p)
+    plan = plan_for(p)
+    ref, oob = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert oob == 0
+    got = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    assert rel_l2(got, ref) <= REL_L2_FP32
+    scale = float(np.max(np.abs(ref)))
+    for i in list(range(len(corners))) + list(range(5000, 5000 + len(corners))):
+        assert abs(got[i] - ref[i]) <= 1e-5 * scale, i
+    plan.sort(t["uvw"])
+    assert np.array_equal(plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy(), got)
+    vin = torch.from_numpy(wl.complex_noise(31, p.n_vis, 1.0)).to(device())
+    g1 = plan.adjoint(vin, t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    g2 = plan.adjoint(vin, t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+    assert np.array_equal(g1, g2)
+    ref_g, _ = oracle.grid(vin.cpu().numpy(), p.g_uv, p.g_w, p.uvw, p.offsets, plan.shape)
+    assert rel_l2(g1, ref_g) <= REL_L2_FP32
+    del t
+    torch.cuda.empty_cache()
