@@ -1241,7 +1241,7 @@ def bench_study(steps, warmup):
     measures), N per subgrid from 2^8 to 2^20, either equal for every subgrid
     or rising linearly to N in the last one; for each, the gather kernel
     mappings (through the caches with one or 64 visibilities per tile, and
-    LDS-staged with 12 KiB or 16 KiB boxes), in input order and after the
+    LDS-staged with 12 KiB or 18 KiB boxes), in input order and after the
     plan-time work order. Median kernel time over the timed launches."""
     import numpy as np
     import torch
@@ -1257,7 +1257,7 @@ def bench_study(steps, warmup):
     # and with LDS boxes, and the D1 mapping (two visibilities per
     # wavefront, accumulation along v)
     mappings = [("D4-like cache gather, n_b 1", 0, 1), ("D4-like cache gather, n_b 64", 0, 64),
-                ("D4-like LDS box 12 KiB, n_b 32", 2, 32), ("D4-like LDS box 16 KiB, n_b 64", 4, 64),
+                ("D4-like LDS box 12 KiB, n_b 32", 2, 32), ("D4-like LDS box 18 KiB, n_b 64", 4, 64),
                 ("D1-like, n_b 32", 6, 32), ("D1-like, n_b 64", 6, 64)]
     rows = []
     for scenario in ("equal", "ramp"):

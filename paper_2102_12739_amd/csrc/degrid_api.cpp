@@ -380,7 +380,7 @@ void tune_cache_store(const std::string& key, int32_t n_b, int32_t variant, int3
 }
 
 // Default tile size and kernel variant when neither the caller nor the tuning
-// cache fixes them: complex float32 stages tiles in 16 KiB LDS boxes; the
+// cache fixes them: complex float32 stages tiles in 18 KiB LDS boxes; the
 // 16-bit storage types gather through the caches (their cells are half as
 // wide, and the staging copy costs more than it saves).
 constexpr int32_t kDefaultNb = 64;

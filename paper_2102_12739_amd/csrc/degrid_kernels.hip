@@ -204,6 +204,11 @@ __global__ __launch_bounds__(kBlockThreads, degrid_min_blocks(G, BOX)) void degr
     using GT = GridTraits<G>;
     static_assert(NB % 8 == 0 && NB <= kMaxNb, "tile size");
     static_assert(!D1 || BOX == 0, "the D1 mapping gathers through the caches");
+    // the staging copy below fills whole steps of 64 slots, also past the
+    // box's last slot (with zeros), so each plane must hold a multiple of 64
+    // 16-byte slots: complex64 boxes are multiples of 2 KiB, 16-bit ones of
+    // 1 KiB
+    static_assert(BOX % (kWave * 16 * (G == kGridC64 ? 2 : 1)) == 0, "box size");
     constexpr int kBoxBytes = BOX > 0 ? BOX : 16;
     constexpr uint32_t kPlane1 = kBoxBytes / 2;   // complex64: w 2-3 of every slot
     __shared__ float2 s_out[kWavesPerBlock][NB];

@@ -702,7 +702,11 @@ __device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, i
 }
 
 // Kernel variants: (LDS box per wavefront in bytes, largest tile, deep).
-// Box 0 gathers through the caches only. A deep variant reads the 4 w values
+// Box 0 gathers through the caches only. A box is a multiple of 2 KiB (the
+// staging copy fills whole steps of 64 slots of 32 bytes). The largest, 18
+// KiB, lets two workgroups of four wavefronts (boxes and 512-byte output
+// staging) fit the CU's 160 KiB of LDS; it holds dense 64-visibility tiles
+// that a 16 KiB box does not (rows of 24 slots: 24 rows instead of 21). A deep variant reads the 4 w values
 // of a tap with loads of one value each (naturally aligned at any first w),
 // for subgrids with more w planes than the w support; it never stages.
 // A D1 variant maps the lanes as the paper's kernel D1 (two visibilities
@@ -711,7 +715,7 @@ __device__ __forceinline__ void gather_tile(float2* out, int count, int a_off, i
 // subgrids deeper than the w support, and never stages.
 struct Variant { int box; int nb; bool deep; bool d1; };
 constexpr Variant kVariants[] = {{0, 64, false, false},     {8192, 32, false, false},  {12288, 32, false, false},
-                                 {16384, 32, false, false}, {16384, 64, false, false}, {0, 64, true, false},
+                                 {16384, 32, false, false}, {18432, 64, false, false}, {0, 64, true, false},
                                  {0, 64, false, true}};
 static_assert(kVariants[kD1Variant].d1 && kVariants[kD1Variant].box == 0, "D1 variant index");
 static_assert(kVariants[kDeepVariant].deep && kVariants[kDeepVariant].box == 0, "deep variant index");
