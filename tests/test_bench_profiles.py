@@ -96,3 +96,59 @@ def test_memory_path_arithmetic():
     assert m["l2_reads_in_flight_per_cu"] == pytest.approx(4000.0 * 500.0 / cu_cycles)
     assert m["waves_in_waitcnt_pct"] == pytest.approx(25.0)
     assert bench.memory_path({"GRBM_GUI_ACTIVE": 1.0}, 1) is None
+
+
+def _write_csv(path, header, rows):
+    import csv
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_summarize_pmc_on_a_synthetic_profiler_tree(tmp_path, monkeypatch):
+    """bench.py --summarize-pmc over hand-made rocprofv3 CSV files: the first
+    dispatch of each pass is dropped (the untimed warmup), counters of one
+    dispatch are summed over their rows and averaged over dispatches, HBM
+    bytes are the FETCH/WRITE counts scaled by the copy calibration, and a
+    leg whose runs printed two source hashes is marked stale (None)."""
+    root = tmp_path / "runs"
+    counters_file = tmp_path / "counters.json"
+    monkeypatch.setattr(bench, "COUNTERS_FILE", str(counters_file))
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    k = "void dg::degrid_kernel<0, 0, 18432, 64, false, false>(dg::LaunchParams)"
+    # copy calibration: 1 GiB read as 2^19 KiB and written as 2^20 KiB
+    _write_csv(str(root / "copy__FETCH_SIZE" / "run_counter_collection.csv"), hdr,
+               [[1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 9e9], [2, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 2 ** 19]])
+    _write_csv(str(root / "copy__WRITE_SIZE" / "run_counter_collection.csv"), hdr,
+               [[1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 9e9], [2, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 2 ** 20]])
+    # latency leg: warmup dispatch 1 (ignored), then dispatches 2 and 3;
+    # dispatch 2 reports FETCH_SIZE in two rows (instances) that add up
+    _write_csv(str(root / "latency__FETCH_SIZE" / "run_counter_collection.csv"), hdr,
+               [[1, k, "FETCH_SIZE", 1e9], [2, k, "FETCH_SIZE", 60.0], [2, k, "FETCH_SIZE", 40.0],
+                [3, k, "FETCH_SIZE", 300.0], [3, "void other_kernel()", "FETCH_SIZE", 7e9]])
+    _write_csv(str(root / "latency__WRITE_SIZE" / "run_counter_collection.csv"), hdr,
+               [[1, k, "WRITE_SIZE", 1e9], [2, k, "WRITE_SIZE", 10.0], [3, k, "WRITE_SIZE", 30.0]])
+    _write_csv(str(root / "latency__stats" / "run_kernel_trace.csv"),
+               ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+               [[1, k, 0, 999999], [2, k, 1000, 7000], [3, k, 9000, 17000]])
+    line = json.dumps({"leg": "latency", "source_sha256_16": "aaaa"})
+    (root / "latency__FETCH_SIZE.log").write_text("noise\n" + line + "\n")
+    bench.summarize_pmc(str(root))
+    out = json.loads(counters_file.read_text())
+    cal = out["calibration"]
+    assert cal["fetch_scale"] == pytest.approx(2.0) and cal["write_scale"] == pytest.approx(1.0)
+    le = out["legs"]["latency"]
+    ke = le["kernels"]["degrid_kernel"]
+    assert ke["counters"]["FETCH_SIZE"] == pytest.approx(200.0)     # (100 + 300) / 2
+    assert ke["counters"]["WRITE_SIZE"] == pytest.approx(20.0)      # (10 + 30) / 2
+    assert ke["hbm_bytes"] == pytest.approx(1024.0 * (200.0 * 2.0 + 20.0 * 1.0))
+    assert ke["duration_us"] == pytest.approx(7.0)                  # (6000 + 8000) ns / 2
+    assert le["source_sha256_16"] == "aaaa"
+    assert le["visibilities"] == 2048 and le["compulsory_bytes"] > 2048 * 32
+    assert (tmp_path / "counters.md").exists()
+    # a second hash among the leg's runs makes the leg's counters stale
+    (root / "latency__WRITE_SIZE.log").write_text(json.dumps({"leg": "latency", "source_sha256_16": "bbbb"}) + "\n")
+    bench.summarize_pmc(str(root))
+    assert json.loads(counters_file.read_text())["legs"]["latency"]["source_sha256_16"] is None
