@@ -302,9 +302,12 @@ dg_status degrid_destroy(dg_plan p);
  * 2 warns that uneven visibility counts per subgrid leave most blocks of the
  * Eq. (1) launch idle, and Section 3 measures throughput against the counts;
  * one queue over the tiles of several problems keeps the device full.) The
- * plans must stay alive while the batch exists. Allocates the batch's tile
- * list, queue and per-problem argument table. DG_ERR_UNSUPPORTED for more
- * than 65535 plans or 2^31 - 1 tiles in all.
+ * plans must stay alive while the batch exists. The batch runs one gather
+ * kernel, that of the plan with the most visibilities (degrid_batch_tune
+ * gives every plan the same one); DG_ERR_INVALID_ARG if another plan's tiles
+ * are larger than that kernel takes. Allocates the batch's tile list, queue
+ * and per-problem argument table. DG_ERR_UNSUPPORTED for more than 65535
+ * plans or 2^31 - 1 tiles in all.
  */
 dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out);
 

@@ -898,9 +898,14 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
     if (!b) return fail(DG_ERR_NOMEM, "host allocation of the batch failed");
     b->plans.assign(plans, plans + n);
     for (int32_t i = 0; i < n; ++i) b->plan_versions.push_back(plans[i]->version);
-    // one kernel for the whole batch: plan 0's, or the deep one if any plan
-    // has subgrids deeper than the w support
-    b->variant = plans[0]->variant;
+    // one kernel for the whole batch: that of the plan with the most
+    // visibilities (a tiny plan defaults to the cache gather, which would slow
+    // the others down; the tuner gives every plan the same one), or the deep
+    // one if any plan has subgrids deeper than the w support
+    int32_t lead = 0;
+    for (int32_t i = 1; i < n; ++i)
+        if (plans[i]->offsets.back() > plans[lead]->offsets.back()) lead = i;
+    b->variant = plans[lead]->variant;
     for (int32_t i = 0; i < n; ++i)
         if (!variant_allowed(plans[i]->desc, b->variant)) b->variant = kDeepVariant;
     b->grid_dtype = plans[0]->desc.grid_dtype;
@@ -919,7 +924,7 @@ dg_status degrid_batch_plan(const dg_plan* plans, int32_t n, dg_batch* out) {
         for (Tile t : plans[i]->tiles) {
             if (t.count > max_nb) {
                 degrid_batch_destroy(b);
-                return fail(DG_ERR_INVALID_ARG, "plan %d has tiles of %d visibilities; plan 0's kernel takes at most %d",
+                return fail(DG_ERR_INVALID_ARG, "plan %d has tiles of %d visibilities; the batch's kernel takes at most %d",
                             i, (int)t.count, max_nb);
             }
             t.problem = (uint16_t)i;

@@ -229,3 +229,26 @@ def test_batched_workload_16_bit_forms_full_size(grid_dtype, gcf_dtype):
     assert (err[0] / err[1]) ** 0.5 <= (3e-3 if grid_dtype == "cbf16" else 1e-3)
     batch.close()
     del ts
+
+
+def test_batch_led_by_a_tiny_plan_runs_its_largest_plans_kernel():
+    """A tiny first plan (2048 visibilities: its default is the cache gather)
+    batched with a large sorted plan (fitted tiles for the staged gather):
+    the batch runs the large plan's kernel over both, and every output equals
+    its plan's own launch bit for bit and the oracle."""
+    tiny = wl.plain_line(seed=0)
+    big = wl.make_problem("batch-lead", [30000, 20000, 15000], seed=43, kind="mixed")
+    announce("batch led by a tiny plan")
+    ts = [upload(tiny), upload(big)]
+    plans = [plan_for(tiny), plan_for(big)]
+    plans[1].sort(ts[1]["uvw"])
+    assert plans[0].info()["kernel"] == 0 and plans[1].info()["kernel"] != 0
+    singles = [pl.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy() for pl, t in zip(plans, ts)]
+    batch = Batch(plans)
+    outs = [torch.full((p.n_vis,), float("nan"), dtype=torch.complex64, device=device()) for p in (tiny, big)]
+    batch.execute([(t["sub"], t["g_uv"], t["g_w"], t["uvw"]) for t in ts], outs=outs)
+    torch.cuda.synchronize()
+    for o, single, p in zip(outs, singles, (tiny, big)):
+        got = o.cpu().numpy()
+        assert np.array_equal(got, single)
+        assert rel_l2(got, oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)[0]) <= REL_L2_FP32
