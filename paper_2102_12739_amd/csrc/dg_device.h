@@ -590,6 +590,17 @@ __device__ __forceinline__ float4 load_gw_row(uint64_t g_w, uint32_t off) {
 }
 
 
+// sum_t g[t] * x[t] for one G_w row, in the order ((g0 x0 + g1 x1) + g2 x2)
+// + g3 x3. For a 16-bit table the first product is also a fused
+// multiply-add (with 0), so that every product takes the 16-bit weight as
+// it is (v_fma_mix_f32) instead of a conversion and a multiply; the sum is
+// the same, but for the sign of an exact zero.
+template <int F>
+__device__ __forceinline__ float wsum4(float4 g, const float (&x)[4]) {
+    const float first = F == kGcfF32 ? g.x * x[0] : __builtin_fmaf(g.x, x[0], 0.0f);
+    return __builtin_fmaf(g.w, x[3], __builtin_fmaf(g.z, x[2], __builtin_fmaf(g.y, x[1], first)));
+}
+
 // Sum over the 64 lanes in float64, in a fixed butterfly order (the same
 // bits on every run).
 __device__ __forceinline__ double wave_sum_f64(double x) {
@@ -672,8 +683,8 @@ __device__ __forceinline__ void sum8(const Fetch8<G>& f, const float* gv, uint32
             const float4 gw = load_gw_row<F>(g_w, (uint32_t)__builtin_amdgcn_readlane((int)gw_off, g0 + k));
             float re[4], im[4];
             widen_w4<G>(f.raw[k], re, im);
-            sr = gw.x * re[0] + gw.y * re[1] + gw.z * re[2] + gw.w * re[3];
-            si = gw.x * im[0] + gw.y * im[1] + gw.z * im[2] + gw.w * im[3];
+            sr = wsum4<F>(gw, re);
+            si = wsum4<F>(gw, im);
         }
         pre[k] = gv[k] * sr;
         pim[k] = gv[k] * si;

@@ -160,8 +160,8 @@ __global__ __launch_bounds__(kBlockThreads) void table_grad_kernel(TableGradPara
                         float re[4], im[4];
                         widen_w4<G>(buf[cur].raw[k], re, im);
                         const float4 gw = gwr[k];
-                        const float sr = gw.x * re[0] + gw.y * re[1] + gw.z * re[2] + gw.w * re[3];
-                        const float si = gw.x * im[0] + gw.y * im[1] + gw.z * im[2] + gw.w * im[3];
+                        const float sr = wsum4<F>(gw, re);
+                        const float si = wsum4<F>(gw, im);
                         val[k] = gre[k] * sr + gim[k] * si;
                     }
 #pragma unroll
