@@ -332,11 +332,18 @@ N_CU = 256   # compute units of the MI355X
 N_XCD = 8    # accelerator complex dies; GRBM_GUI_ACTIVE counts once per die
 
 
-def memory_path(c, n_vis):
+# Kernels shorter than this have no share of wave cycles in s_waitcnt: its
+# two counters come from different rocprofv3 passes, and for a kernel of a
+# few microseconds their run-to-run spread is larger than the share.
+WAITCNT_MIN_US = 100.0
+
+
+def memory_path(c, n_vis, duration_us=None):
     """Vector-memory path figures of one kernel from its counters, or None:
     per-CU busy and stall shares of the texture data unit (TD) and the vector
     L1 (TCP), the L1-to-L2 read latency, L2 reads per visibility and in
-    flight per CU, and the share of wave cycles spent in s_waitcnt."""
+    flight per CU, and the share of wave cycles spent in s_waitcnt (None for
+    kernels shorter than WAITCNT_MIN_US when their duration is given)."""
     need = ("GRBM_GUI_ACTIVE", "TD_TD_BUSY_sum", "TCP_TCC_READ_REQ_sum")
     if any(c.get(k) is None for k in need) or not c["GRBM_GUI_ACTIVE"]:
         return None
@@ -353,7 +360,8 @@ def memory_path(c, n_vis):
             "l2_reads_per_vis": req / n_vis if n_vis else None,
             "l2_reads_in_flight_per_cu": lat / cu_cycles if lat is not None else None,
             "waves_in_waitcnt_pct": 100.0 * c["SQ_WAIT_ANY"] / c["SQ_WAVE_CYCLES"]
-            if c.get("SQ_WAIT_ANY") is not None and c.get("SQ_WAVE_CYCLES") else None}
+            if c.get("SQ_WAIT_ANY") is not None and c.get("SQ_WAVE_CYCLES")
+            and (duration_us is None or duration_us >= WAITCNT_MIN_US) else None}
 
 
 def counters_markdown(out):
@@ -425,7 +433,8 @@ def counters_markdown(out):
         "TCP_TCC_READ_REQ_LATENCY_sum / (CUs x cycles); waves in s_waitcnt = SQ_WAIT_ANY / SQ_WAVE_CYCLES.",
         "For kernels of 100 us or more the cycles match the traced duration at 2.26-2.43 GHz; for kernels of",
         "a few tens of microseconds GRBM_GUI_ACTIVE also counts the profiler's per-dispatch overhead, so their",
-        "shares read low.",
+        "shares read low. The s_waitcnt share takes its two counters from different passes: it is given for",
+        "kernels of 100 us or more only.",
         "",
         "| leg | kernel | TA busy % | TD busy % | TD waiting on L1 % | L1 stalled on misses % | "
         "L2 read latency (cycles) | L2 reads / vis | L2 reads in flight / CU | waves in s_waitcnt % |",
@@ -433,7 +442,7 @@ def counters_markdown(out):
     ]
     for leg, le in sorted(out["legs"].items()):
         for k, ke in sorted(le["kernels"].items()):
-            m = memory_path(ke["counters"], le.get("visibilities") or 0)
+            m = memory_path(ke["counters"], le.get("visibilities") or 0, ke.get("duration_us"))
             if m is None:
                 continue
             f = lambda x, fmt: (fmt.format(x) if x is not None else "-")   # noqa: E731

@@ -45,7 +45,7 @@ def test_every_fraction_of_a_peak_is_at_most_one(leg):
             assert lds / t / 1e9 / bench.LDS_PEAK_GBS <= 1.0, (leg, name)
         if cn.get("SQ_INSTS_VALU") is not None:
             assert cn["SQ_INSTS_VALU"] / t / 1e9 / bench.VALU_PEAK_GINST <= 1.0, (leg, name)
-        m = bench.memory_path(cn, c["visibilities"])
+        m = bench.memory_path(cn, c["visibilities"], us)
         if m is not None:
             for k in ("td_busy_pct", "td_wait_cache_pct", "tcp_pending_stall_pct", "ta_busy_avr_pct",
                       "waves_in_waitcnt_pct"):
@@ -95,6 +95,8 @@ def test_memory_path_arithmetic():
     assert m["l2_reads_per_vis"] == pytest.approx(4.0)
     assert m["l2_reads_in_flight_per_cu"] == pytest.approx(4000.0 * 500.0 / cu_cycles)
     assert m["waves_in_waitcnt_pct"] == pytest.approx(25.0)
+    assert bench.memory_path(c, 1000, bench.WAITCNT_MIN_US)["waves_in_waitcnt_pct"] == pytest.approx(25.0)
+    assert bench.memory_path(c, 1000, 0.5 * bench.WAITCNT_MIN_US)["waves_in_waitcnt_pct"] is None
     assert bench.memory_path({"GRBM_GUI_ACTIVE": 1.0}, 1) is None
 
 
