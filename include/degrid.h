@@ -135,6 +135,13 @@ typedef struct {
  * n_w != 4 uses the one kernel variant that reads taps starting at any w
  * (no LDS staging); degrid_plan_set_kernel refuses the others for it, and
  * its adjoint scatters with float32 atomics even after degrid_plan_sort.
+ * With d->n_b == 0 the library chooses the tile size and kernel variant: the
+ * choice recorded by degrid_tune in the DG_TUNE_CACHE file for this device
+ * and problem shape class if there is one; else tiles of 64 visibilities
+ * (smaller, a multiple of 8, when the plan has fewer than 16 visibilities per
+ * resident wavefront), staged through LDS boxes for complex float32 storage
+ * and gathered through the caches for the 16-bit storage types and for plans
+ * of at most two resident wavefronts' worth of visibilities.
  */
 dg_status degrid_plan(const dg_desc* d, int64_t n_subgrids, const int64_t* vis_offsets,
                       hipStream_t stream, dg_plan* out);
