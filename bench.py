@@ -129,6 +129,12 @@ LEGS = {
                             kernels=("table_grad_kernel", "zero_f32_kernel")),
     "latency": dict(source="degrid", workload="plain", grid="c64", gcf="f32", op="degrid",
                     kernels=("degrid_kernel",)),
+    # the eight batched problems in one launch of a Batch (replayed HIP graph),
+    # with each plan's default kernel (the batch tuner's choice in the bench)
+    "batched": dict(source="degrid", workload="batched", grid="c64", gcf="f32", op="batch",
+                    kernels=("degrid_kernel",)),
+    "batched_bf16": dict(source="degrid", workload="batched", grid="cbf16", gcf="bf16", op="batch",
+                         kernels=("degrid_kernel",)),
 }
 
 
@@ -146,6 +152,8 @@ def run_leg(name, steps, warmup, cold, kernel=None, nb=None):
         ms = launch_times(lambda: b.copy_(a), warmup + steps)[warmup:]
         return {"leg": name, "bytes": 1 << 30, "launches": steps, "kernel_ms": percentiles(ms)}
     leg = LEGS[name]
+    if leg["op"] == "batch":
+        return run_batch_leg(name, leg, steps, warmup, cold, kernel, nb)
     p = {"paper": lambda: wl.paper_scale(seed=1), "diff": lambda: wl.differentiation(seed=4),
          "plain": lambda: wl.plain_line(seed=0)}[leg["workload"]]()
     sub, g_uv, g_w, uvw = upload_inputs(p, leg["grid"], leg["gcf"])
@@ -201,6 +209,39 @@ def run_leg(name, steps, warmup, cold, kernel=None, nb=None):
            "plan": plan.info(), "source_sha256_16": source_hash(leg["source"])}
     log(f"leg {name}: {res['kernel_ms']['median'] * 1e3:.1f} us median over {steps} launches"
         f" ({'cold' if cold else 'warm'})")
+    return res
+
+
+def run_batch_leg(name, leg, steps, warmup, cold, kernel=None, nb=None):
+    """A batched profiling leg: the eight problems of the batched workload
+    (seed 2) as sorted plans in one Batch, launched as run_leg launches."""
+    import torch
+    from paper_2102_12739_amd import workload as wl
+    from paper_2102_12739_amd.degrid import Batch, Plan
+    probs = wl.batched(seed=2)
+    ins = [upload_inputs(q, leg["grid"], leg["gcf"]) for q in probs]
+    plans = []
+    for q, i in zip(probs, ins):
+        pl = Plan(q.offsets, q.n_v, q.n_u, q.n_w, q.os_uv, q.os_w, grid_dtype=leg["grid"], gcf_dtype=leg["gcf"])
+        pl.sort(i[3])
+        if kernel is not None:
+            pl.set_kernel(kernel, nb or 0)
+        plans.append(pl)
+    outs = [torch.empty(q.n_vis, dtype=torch.complex64, device="cuda:0") for q in probs]
+    batch = Batch(plans)
+    fn = lambda: batch.execute(ins, outs=outs)   # noqa: E731
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ms = cold_launches(fn, steps) if cold else launch_times(fn, steps)
+    n_vis = sum(q.n_vis for q in probs)
+    res = {"leg": name, "workload": "batched-8-problems-seed2", "visibilities": n_vis, "cold": bool(cold),
+           "launches": steps, "kernel_ms": percentiles(ms), "kernel_ms_mean": float(sum(ms) / len(ms)),
+           "plan": {"kernel": plans[0].info()["kernel"], "n_b": plans[0].info()["n_b"]},
+           "source_sha256_16": source_hash(leg["source"])}
+    log(f"leg {name}: {res['kernel_ms']['median'] * 1e3:.1f} us median over {steps} launches"
+        f" ({'cold' if cold else 'warm'})")
+    batch.close()
     return res
 
 
@@ -297,16 +338,17 @@ def summarize_pmc(root):
             le["duration_us"] = sum(k["duration_us"] for k in ks)
     from paper_2102_12739_amd import workload as wl
     # (coordinates and tables only: the subgrids do not enter the count)
-    works = {"paper": lambda: wl.paper_scale(seed=1, with_grid=False),
-             "diff": lambda: wl.differentiation(seed=4, with_grid=False),
-             "plain": lambda: wl.plain_line(seed=0, with_grid=False)}
+    works = {"paper": lambda: [wl.paper_scale(seed=1, with_grid=False)],
+             "diff": lambda: [wl.differentiation(seed=4, with_grid=False)],
+             "plain": lambda: [wl.plain_line(seed=0, with_grid=False)],
+             "batched": lambda: wl.batched(seed=2, with_grid=False)}
     comp = {}
     for leg, le in out["legs"].items():
         w = LEGS[leg]["workload"]
         elem = 8 if LEGS[leg]["grid"] == "c64" else 4
         if (w, elem) not in comp:
-            pw = works[w]()
-            comp[(w, elem)] = (compulsory_bytes(pw, elem), pw.n_vis)
+            pws = works[w]()
+            comp[(w, elem)] = (sum(compulsory_bytes(q, elem) for q in pws), sum(q.n_vis for q in pws))
         le["compulsory_bytes"], le["visibilities"] = comp[(w, elem)]
     with open(COUNTERS_FILE, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
