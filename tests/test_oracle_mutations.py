@@ -45,6 +45,14 @@ MUTANTS = {
     "tgrad_w_taps_reversed": ("grad_g_w[(int64_t)o_w * support_w + tw] +=",
                               "grad_g_w[(int64_t)o_w * support_w + (support_w - 1 - tw)] +="),
     "tgrad_w_sum_skips_last_tap": ("c_re += gw[tw] * a_re;", "c_re += (tw < support_w - 1) ? gw[tw] * a_re : 0.0;"),
+    "real_sign": ("re += weight * subgrids[2 * cell];", "re -= weight * subgrids[2 * cell];"),
+    "grid_real_sign": ("out[2 * cell] += weight * vis[2 * i];", "out[2 * cell] -= weight * vis[2 * i];"),
+    "lower_bound_strict": ("!(first >= 0.0)", "!(first > 0.0)"),
+    "cell_not_floored": ("double n = floor(k / (double)os);", "double n = k / (double)os;"),
+    "w_axis_bounded_by_n_v": ("uvw_i[2], g->os_w, g->support_w, g->n_w,", "uvw_i[2], g->os_w, g->support_w, g->n_v,"),
+    "grid_v_tap_dropped": ("for (int32_t tv = 0; tv < support_uv; ++tv)\n                for (int32_t tu = 0; tu < support_uv; ++tu)\n                    for (int32_t tw = 0; tw < support_w; ++tw) {\n                        double weight = gw[tw] * guv[tv * support_uv + tu];\n                        int64_t cell = (((y",
+                           "for (int32_t tv = 0; tv < support_uv - 1; ++tv)\n                for (int32_t tu = 0; tu < support_uv; ++tu)\n                    for (int32_t tw = 0; tw < support_w; ++tw) {\n                        double weight = gw[tw] * guv[tv * support_uv + tu];\n                        int64_t cell = (((y"),
+    "tgrad_uv_uses_w_of_first_tap": ("c_re += gw[tw] * a_re;", "c_re += gw[0] * a_re;"),
 }
 
 
