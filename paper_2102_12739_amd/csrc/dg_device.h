@@ -182,6 +182,10 @@ __device__ __forceinline__ int claim_resolve(const QueueSpec& qs, const StaticDe
 // (vmcnt 0) before its increment of the finished-workgroup counter orders
 // the two, and the last workgroup's exchange then reads every count. No L2
 // write-back is needed (the kernel's own end writes the caches back).
+// kGrouped: for kernels whose workgroups all end at about the same time, a
+// grid of more than kDoneFlat workgroups counts in two levels (group
+// counters, then `done`).
+template <bool kGrouped = false>
 __device__ __forceinline__ void finish_launch(Ctl* ctl, uint32_t wave_oob) {
     auto* oob = reinterpret_cast<unsigned long long*>(&ctl->oob.v[0]);
     if (lane_id() == 0 && wave_oob != 0u) atomicAdd(&oob[0], (unsigned long long)wave_oob);
@@ -189,14 +193,27 @@ __device__ __forceinline__ void finish_launch(Ctl* ctl, uint32_t wave_oob) {
     wait_vmem_all();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t prev = atomicAdd(&ctl->done.v[0], 1u);
-        if (prev == gridDim.x - 1) {
-            const unsigned long long total = atomicExch(&oob[0], 0ull);
-            atomicExch(&oob[1], total);
-            for (int q = 0; q < kMaxQueues; ++q) atomicExch(&ctl->cursor[q].v[0], 0u);
-            atomicExch(&ctl->done.v[0], 0u);
-        }
+    if (threadIdx.x != 0) return;
+    const uint32_t n = gridDim.x;
+    const bool grouped = kGrouped && n > (uint32_t)kDoneFlat;
+    bool last;
+    if (!grouped) {
+        last = atomicAdd(&ctl->done.v[0], 1u) == n - 1;
+    } else {
+        // the last workgroup of a group has seen every increment of its
+        // group, and the last of the groups every group's last
+        const uint32_t g = blockIdx.x % kDoneGroups;
+        const uint32_t in_group = (n - g + kDoneGroups - 1) / kDoneGroups;
+        last = atomicAdd(&ctl->group[g].v[0], 1u) == in_group - 1 &&
+               atomicAdd(&ctl->done.v[0], 1u) == (uint32_t)kDoneGroups - 1;
+    }
+    if (last) {
+        const unsigned long long total = atomicExch(&oob[0], 0ull);
+        atomicExch(&oob[1], total);
+        for (int q = 0; q < kMaxQueues; ++q) atomicExch(&ctl->cursor[q].v[0], 0u);
+        if (grouped)
+            for (int q = 0; q < kDoneGroups; ++q) atomicExch(&ctl->group[q].v[0], 0u);
+        atomicExch(&ctl->done.v[0], 0u);
     }
 }
 

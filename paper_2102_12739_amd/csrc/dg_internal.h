@@ -43,14 +43,22 @@ struct Problem {
 // each, so atomics from different XCDs do not share a line), the count of
 // finished workgroups, and the out-of-range counters. The last workgroup of
 // every launch resets the cursors and the counters, so a launch needs no
-// separate reset and can be replayed from a graph. (Every workgroup's end is
-// one atomic on the same counter, about 20 ns apiece when they queue, so
-// grids stay near the device's resident capacity.)
+// separate reset and can be replayed from a graph. Atomics on one counter
+// take about 20 ns apiece when they queue, so with one counter the end of a
+// launch whose workgroups all finish together waits on a chain as long as
+// the grid. Such a kernel (the adjoint's fix-up pass), on a grid of more than
+// kDoneFlat workgroups, counts their ends in two levels: into one of
+// kDoneGroups group counters (workgroup b into b mod kDoneGroups), and the
+// last of each group into `done`. Other kernels, and small grids, count into
+// `done` directly, which saves the second, dependent atomic.
+constexpr int kDoneGroups = 8;
+constexpr int kDoneFlat = 64;
 struct alignas(128) CtlLine { uint32_t v[32]; };
 struct Ctl {
     CtlLine cursor[kMaxQueues];
     CtlLine done;
     CtlLine oob;   // v[0..1]: running count (u64), v[2..3]: count of the last launch
+    CtlLine group[kDoneGroups];
 };
 
 struct LaunchParams {

@@ -333,66 +333,88 @@ __global__ __launch_bounds__(kBlockThreads) void grid_owner_kernel(OwnerParams P
 }
 
 // Visibilities the owner pass skipped (first tap differs from the plan's),
-// added with atomics by whole wavefronts, and the out-of-range count.
+// added with atomics by whole wavefronts, and the out-of-range count. Each
+// lane loads the coordinates and plan starts of kFixupPerLane visibilities
+// (64 apart) before testing any of them, so one pass over the coordinates
+// waits out one memory latency per kFixupPerLane visibilities.
+constexpr int kFixupPerLane = 4;
+
 template <int F>
 __global__ __launch_bounds__(kBlockThreads) void grid_fixup_kernel(Problem pr, const int64_t* offsets,
                                                                    int64_t n_sub, int64_t n_vis,
                                                                    const uint32_t* plan_start, Ctl* ctl) {
     const int lane = lane_id();
     const int tv = lane >> 3, tu = lane & 7;
+    const int64_t lane_cell = (int64_t)(tv * pr.n_u + tu) * pr.n_w;
     uint32_t wave_oob = 0;
     const int64_t n_waves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t first = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    for (int64_t w0 = first * kWave; w0 < n_vis; w0 += n_waves * kWave) {
-        const int64_t i = w0 + lane;
-        int32_t cell = 0, tab = 0, ow = 0, x0 = 0, y0 = 0;
-        bool in_range = false, redo = false;
-        if (i < n_vis) {
+    constexpr int64_t kSpan = (int64_t)kWave * kFixupPerLane;
+    for (int64_t w0 = first * kSpan; w0 < n_vis; w0 += n_waves * kSpan) {
+        double cu[kFixupPerLane], cv[kFixupPerLane], cw[kFixupPerLane];
+        uint32_t ps[kFixupPerLane];
+        // branch-free loads (a lane past the end re-reads the last
+        // visibility and ignores it), so all of them are in flight at once
+#pragma unroll
+        for (int k = 0; k < kFixupPerLane; ++k) {
+            int64_t i = w0 + k * kWave + lane;
+            i = i < n_vis ? i : n_vis - 1;
             const double* uv = pr.uvw + 3 * i;
-            in_range = coords_from(pr, uv[0], uv[1], uv[2], cell, tab, ow, x0, y0);
-            redo = in_range && (((uint32_t)y0 << 16) | (uint32_t)x0) != plan_start[i];
+            cu[k] = uv[0];
+            cv[k] = uv[1];
+            cw[k] = uv[2];
+            ps[k] = plan_start[i];
         }
-        wave_oob += (uint32_t)__popcll(__ballot(i < n_vis && !in_range));
-        uint64_t mask = __ballot(redo);
-        if (mask == 0) continue;
-        // subgrid of each visibility to redo
-        int64_t sub = 0;
-        if (redo) {
-            int64_t lo = 0, hi = n_sub;
-            while (hi - lo > 1) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (offsets[mid] <= i) lo = mid; else hi = mid;
+#pragma unroll
+        for (int k = 0; k < kFixupPerLane; ++k) {
+            const int64_t i = w0 + k * kWave + lane;
+            int32_t cell = 0, tab = 0, ow = 0, x0 = 0, y0 = 0;
+            bool in_range = false, redo = false;
+            if (i < n_vis) {
+                in_range = coords_from(pr, cu[k], cv[k], cw[k], cell, tab, ow, x0, y0);
+                redo = in_range && (((uint32_t)y0 << 16) | (uint32_t)x0) != ps[k];
             }
-            sub = lo;
-        }
-        float c[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) c[q] = 0.0f;
-        if (redo) {
-            const float2 vv = static_cast<const float2*>(pr.vis)[i];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float gw = load_gcf<F>(pr.g_w, ow * kSupportW + k);
-                c[2 * k] = gw * vv.x;
-                c[2 * k + 1] = gw * vv.y;
+            wave_oob += (uint32_t)__popcll(__ballot(i < n_vis && !in_range));
+            uint64_t mask = __ballot(redo);
+            if (mask == 0) continue;
+            // subgrid of each visibility to redo
+            int64_t sub = 0;
+            if (redo) {
+                int64_t lo = 0, hi = n_sub;
+                while (hi - lo > 1) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (offsets[mid] <= i) lo = mid; else hi = mid;
+                }
+                sub = lo;
             }
-        }
-        const int64_t lane_cell = (int64_t)(tv * pr.n_u + tu) * pr.n_w;
-        while (mask) {
-            const int j = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            const int64_t sj = ((int64_t)__builtin_amdgcn_readlane((int)(sub >> 32), j) << 32) |
-                               (uint32_t)__builtin_amdgcn_readlane((int)sub, j);
-            const int cj = __builtin_amdgcn_readlane(cell, j);
-            const int tj = __builtin_amdgcn_readlane(tab, j);
-            const float g = load_gcf<F>(pr.g_uv, (int64_t)tj + lane);
-            float* dst = static_cast<float*>(pr.grid_out) + 2 * (sj * pr.cells_per_sub + cj + lane_cell);
+            float c[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                unsafeAtomicAdd(dst + q, g * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c[q]), j)));
+            for (int q = 0; q < 8; ++q) c[q] = 0.0f;
+            if (redo) {
+                const float2 vv = static_cast<const float2*>(pr.vis)[i];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float gw = load_gcf<F>(pr.g_w, ow * kSupportW + t);
+                    c[2 * t] = gw * vv.x;
+                    c[2 * t + 1] = gw * vv.y;
+                }
+            }
+            while (mask) {
+                const int j = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const int64_t sj = ((int64_t)__builtin_amdgcn_readlane((int)(sub >> 32), j) << 32) |
+                                   (uint32_t)__builtin_amdgcn_readlane((int)sub, j);
+                const int cj = __builtin_amdgcn_readlane(cell, j);
+                const int tj = __builtin_amdgcn_readlane(tab, j);
+                const float g = load_gcf<F>(pr.g_uv, (int64_t)tj + lane);
+                float* dst = static_cast<float*>(pr.grid_out) + 2 * (sj * pr.cells_per_sub + cj + lane_cell);
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    unsafeAtomicAdd(dst + q, g * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c[q]), j)));
+            }
         }
     }
-    finish_launch(ctl, wave_oob);
+    finish_launch<true>(ctl, wave_oob);
 }
 
 }  // namespace
@@ -482,7 +504,8 @@ hipError_t owner_kernel_occupancy(int gcf_kind, int* n) {
 hipError_t launch_grid_fixup(const Problem& pr, const int64_t* vis_offsets, int64_t n_sub, int64_t n_vis,
                              const uint32_t* plan_start, Ctl* ctl, int gcf_kind, int max_blocks,
                              hipStream_t stream) {
-    int64_t blocks = (n_vis + kBlockThreads - 1) / kBlockThreads;
+    const int64_t per_block = (int64_t)kBlockThreads * kFixupPerLane;
+    int64_t blocks = (n_vis + per_block - 1) / per_block;
     blocks = blocks < 1 ? 1 : (blocks > max_blocks ? max_blocks : blocks);
     if (gcf_kind == kGcfF32)
         hipLaunchKernelGGL((grid_fixup_kernel<kGcfF32>), dim3((unsigned)blocks), dim3(kBlockThreads), 0, stream, pr,
