@@ -163,6 +163,40 @@ def test_owner_adjoint_with_coordinates_changed_after_sorting():
     assert rel_l2(f, fref) <= REL_L2_FP32
 
 
+def test_owner_adjoint_fixup_on_a_large_grid_counts_every_launch():
+    """The fix-up pass on more than 64 workgroups, whose ends are counted in
+    two levels (here 196 workgroups: groups of 25 and 24). Moved and
+    out-of-range visibilities are added and counted launch after launch, with
+    forward launches on the same control block in between."""
+    p = wl.make_problem("owner-moved-large", [120000, 80000], seed=31, kind="mixed", n_v=128, n_u=128)
+    announce(f"owner adjoint fix-up, {p.n_vis} visibilities")
+    t = upload(p)
+    plan = plan_for(p)
+    plan.sort(t["uvw"])
+    rng = np.random.default_rng(31)
+    box = wl.interior_box(p.n_v, p.n_u, p.n_w)
+    moved = p.uvw.copy()
+    pick = rng.choice(p.n_vis, p.n_vis // 4, replace=False)
+    for a in (0, 1):
+        moved[pick, a] = np.clip(moved[pick, a] + rng.uniform(-20, 20, len(pick)), box.lo[a], box.hi[a] - 1e-3)
+    moved[pick[:40], 1] = np.nan       # now out of range
+    um = torch.from_numpy(moved).to(device())
+    v = wl.complex_noise(31, p.n_vis, 1.0)
+    vt = torch.from_numpy(v).to(device())
+    ref, oob = oracle.grid(v, p.g_uv, p.g_w, moved, p.offsets, plan.shape)
+    fref, oob0 = oracle.degrid(p.subgrids, p.g_uv, p.g_w, p.uvw, p.offsets)
+    assert oob == 40
+    for _ in range(3):
+        g = plan.adjoint(vt, t["g_uv"], t["g_w"], um).cpu().numpy()
+        assert rel_l2(g, ref) <= REL_L2_FP32
+        assert plan.oob_count() == oob
+        f = plan.execute(t["sub"], t["g_uv"], t["g_w"], t["uvw"]).cpu().numpy()
+        assert rel_l2(f, fref) <= REL_L2_FP32
+        assert plan.oob_count() == oob0
+    del t
+    torch.cuda.empty_cache()
+
+
 def test_owner_adjoint_accumulates():
     p = wl.make_problem("owner-acc", [3000, 2000], seed=30, kind="mixed", n_v=48, n_u=64)
     t = upload(p)
