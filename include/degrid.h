@@ -241,7 +241,8 @@ dg_status degrid_residual(dg_plan p, const void* subgrids, const void* g_uv, con
  * On a plan with a work order (degrid_plan_sort), every 16 x 16-cell block
  * of the output is summed by one wavefront in LDS and written once, so the
  * result has the same bits on every call; visibilities whose coordinates
- * moved since the sort are added by a second pass with float32 atomics. On
+ * moved since the sort are added by a second pass with float32 atomics (so
+ * when some moved, their sums' last bits vary from run to run). On
  * a plan in input order the output is zeroed (by a kernel) and contributions
  * are added with float32 atomics, so the last bits vary from run to run.
  * Asynchronous on 'stream'; allocates nothing.
