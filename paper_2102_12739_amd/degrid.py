@@ -118,25 +118,32 @@ def _stream_handle(stream) -> int:
 
 
 def _ptr(t: torch.Tensor, name: str, dtype=None, shape=None) -> int:
+    """Device pointer of a checked tensor. Runs for every tensor of every
+    call, so each check takes its cheapest form (``is_cuda``, dtype identity,
+    ``torch.Size`` against the expected tuple); ``shape`` is a tuple."""
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
-    if t.device.type != "cuda":
+    if not t.is_cuda:
         raise ValueError(f"{name} must be on a GPU device, got {t.device}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
-    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+    if dtype is not None and t.dtype is not dtype and not (isinstance(dtype, tuple) and t.dtype in dtype):
         raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
-    if shape is not None and tuple(t.shape) != tuple(shape):
+    if shape is not None and t.shape != shape:
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
     return t.data_ptr()
 
 
+_GRID_TENSOR_DTYPE = {"c64": torch.complex64, "cbf16": torch.bfloat16, "cf16": torch.float16}
+_GCF_TENSOR_DTYPE = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+
+
 def _grid_tensor_dtype(grid_dtype: str):
-    return {"c64": torch.complex64, "cbf16": torch.bfloat16, "cf16": torch.float16}[grid_dtype]
+    return _GRID_TENSOR_DTYPE[grid_dtype]
 
 
 def _gcf_tensor_dtype(gcf_dtype: str):
-    return {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[gcf_dtype]
+    return _GCF_TENSOR_DTYPE[gcf_dtype]
 
 
 class Plan:
