@@ -12,12 +12,13 @@
 //
 //  * dL/dG_uv: every visibility adds one value per lane to the 64 contiguous
 //    entries of its (o_v, o_u) block. When the table fits (os_uv <= 16,
-//    64 KiB) the workgroup keeps its own copy in LDS and every other
-//    visibility adds there (one LDS float add, no two lanes on one entry;
-//    the copy is added to the output once at the end), the others straight
-//    to the output with one coalesced float atomic, so that the two atomic
-//    units work side by side. Float atomics make the order, and so the last
-//    bits, depend on timing;
+//    64 KiB) the workgroup keeps its own copy in LDS and seven of every
+//    sixteen visibilities add there (one LDS float add, no two lanes on one
+//    entry; the copy is added to the output once at the end), the others
+//    straight to the output with one coalesced float atomic, so that the two
+//    atomic units work side by side (7/16 measured faster than 3/8 and 1/2,
+//    with caches cold and warm). Float atomics make the order, and so the
+//    last bits, depend on timing;
 //  * dL/dG_w: per w tap, the shares of a group of eight visibilities are
 //    summed over the 64 lanes together (the degrid kernel's eight-way
 //    permlane/DPP reduction), and lane 8m adds visibility m's four sums to
@@ -56,6 +57,9 @@ __device__ __forceinline__ void grad_fetch(GradFetch<G>& f, int g0, int a_off, i
 }
 
 constexpr int kWGroups = 8;   // per-visibility slots of the dL/dG_w sums in LDS
+// bit k: visibility k of a group adds to the LDS copy; even groups take 3
+// of their 8 visibilities there, odd groups 4
+constexpr uint32_t kLdsShareEven = 0x49u, kLdsShareOdd = 0x55u;
 
 // w value tw of one fetched cell, widened to float32.
 template <int G>
@@ -170,9 +174,11 @@ __global__ __launch_bounds__(kBlockThreads) void table_grad_kernel(TableGradPara
                         if (!((live >> j) & 1ull)) continue;   // wave-uniform: no atomic for nothing
                         const int e = __builtin_amdgcn_readlane(tab, j) + lane;
                         // LDS float atomics and global float atomics run in
-                        // different units: alternate visibilities go to each,
-                        // so that the two overlap
-                        if (LDS_UV && (k & 1) == 0)
+                        // different units: 7 of every 16 visibilities go to
+                        // LDS, the others to global memory, so that the two
+                        // overlap
+                        const uint32_t lds_share = ((g0 / kGroup) & 1) ? kLdsShareOdd : kLdsShareEven;
+                        if (LDS_UV && ((lds_share >> k) & 1u))
                             atomicAdd(s_uv + e, val[k]);
                         else
                             atomicAdd(P.grad_uv + e, val[k]);
