@@ -711,12 +711,10 @@ dg_status degrid_table_grad(dg_plan p, const void* subgrids, const void* g_uv, c
     int max_lds = 0;
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(LDS per workgroup)");
-    bool lds_uv = false;
-    size_t lds = 0;
-    table_grad_shape(d.os_uv, d.os_w, grad_g_uv != nullptr, grad_g_w != nullptr, (size_t)max_lds, &lds_uv, &lds);
-    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(2, (int64_t)(160 * 1024) / (int64_t)std::max<size_t>(lds, 1)));
+    // one workgroup of kTableGradThreads per CU (registers allow no second)
+    constexpr int64_t waves = kTableGradThreads / kWave;
     const int64_t blocks = std::max<int64_t>(
-        1, std::min<int64_t>((p->ds.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)std::max(1, p->n_cu) * per_cu));
+        1, std::min<int64_t>((p->ds.n_tiles + waves - 1) / waves, (int64_t)std::max(1, p->n_cu)));
     e = launch_table_grad(tp, d.grid_dtype, d.gcf_dtype, deep_only(d), (int)blocks, (size_t)max_lds, stream);
     if (e != hipSuccess) return hip_fail(e, "table gradient kernel launch");
     p->last_stream = stream;

@@ -14,6 +14,11 @@ constexpr int kSupportW = 4;    // G_w support (Section 2)
 constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kBlockThreads = 256;
 constexpr int kWavesPerBlock = kBlockThreads / kWave;
+// The table-gradient kernel runs one workgroup of eight wavefronts per CU
+// (its registers allow two wavefronts per SIMD), so that eight wavefronts
+// share one LDS copy of dL/dG_uv and half as many copies are added to the
+// output at the end as with two workgroups of four.
+constexpr int kTableGradThreads = 512;
 
 // Invalid-offset sentinel for hardware bounds-checked (buffer) loads: any
 // offset at or above a resource's size returns zero. Subgrids and tables are

@@ -80,7 +80,7 @@ __device__ __forceinline__ void widen_one(const uint32_t (&raw)[GridTraits<G>::k
 
 // LDS_UV: the workgroup accumulates dL/dG_uv in LDS (the table fits).
 template <int G, int F, bool DEEP, bool LDS_UV>
-__global__ __launch_bounds__(kBlockThreads) void table_grad_kernel(TableGradParams P) {
+__global__ __launch_bounds__(kTableGradThreads) void table_grad_kernel(TableGradParams P) {
     // [n_uv] shared by the workgroup (LDS_UV), then [waves][os_w * 4][8]
     extern __shared__ float s_acc[];
     const int lane = lane_id();
@@ -251,7 +251,7 @@ __global__ void zero_f32_kernel(float* p, int64_t n) {
 
 template <int G, int F, bool DEEP, bool LDS_UV>
 hipError_t launch_tg(const TableGradParams& p, int blocks, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((table_grad_kernel<G, F, DEEP, LDS_UV>), dim3(blocks), dim3(kBlockThreads), lds, s, p);
+    hipLaunchKernelGGL((table_grad_kernel<G, F, DEEP, LDS_UV>), dim3(blocks), dim3(kTableGradThreads), lds, s, p);
     return hipGetLastError();
 }
 
@@ -271,7 +271,7 @@ hipError_t launch_tg_d(const TableGradParams& p, bool deep, bool lds_uv, int blo
 void table_grad_shape(int os_uv, int os_w, bool want_uv, bool want_w, size_t max_lds, bool* lds_uv,
                       size_t* lds_bytes) {
     const size_t uv = (size_t)os_uv * os_uv * kSupportUV * kSupportUV * sizeof(float);
-    const size_t w = want_w ? (size_t)kWavesPerBlock * os_w * kSupportW * kWGroups * sizeof(float) : 0;
+    const size_t w = want_w ? (size_t)(kTableGradThreads / kWave) * os_w * kSupportW * kWGroups * sizeof(float) : 0;
     *lds_uv = want_uv && uv <= 65536 && uv + w <= max_lds;
     *lds_bytes = (*lds_uv ? uv : 0) + w;
 }
